@@ -1,0 +1,378 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+None of these re-derives an oracle result with the oracle's own formula:
+Table II is the paper's printed classification, Eq. 3-6 are identities
+between table entries, the encoder is an independent GF(2) convolution,
+the metrics are checked against the correlation and Euclidean forms, the
+dynamic programme against exhaustive search, and the block decomposition
+against full-frame decoding.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00066_amd import datagen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+ALL_CODES = [
+    (3, (0o7, 0o5)),
+    (4, (0o15, 0o17)),
+    (5, (0o23, 0o35)),
+    (6, (0o53, 0o75)),
+    (7, (0o171, 0o133)),
+    (7, (0o133, 0o171, 0o165)),
+    (8, (0o247, 0o371)),
+    (9, (0o557, 0o663, 0o711)),
+    (5, (0o25, 0o27, 0o33, 0o37)),
+    (5, (0o31, 0o27)),        # g_{K-1}=1, g_0=1 on one generator only: not "special"
+    (6, (0o46, 0o73)),        # g_0 = 0 on the first generator
+]
+
+
+def gcol(gens, k):
+    """Code word contributed by register bit k: (g_k^(1) ... g_k^(R)), c^(1) as MSB."""
+    R = len(gens)
+    c = 0
+    for r in range(R):
+        c = (c << 1) | ((gens[r] >> k) & 1)
+    return c
+
+
+def test_table2_classification_exact():
+    """Table II: alpha/beta/gamma/theta of every butterfly of the (171,133) code."""
+    K, gens = 7, (0o171, 0o133)
+    nxt, lab = oracle.trellis(K, gens)
+    seen = set()
+    with open(os.path.join(GOLDEN, "table2_k7_171_133.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            head, states = line.split(":")
+            _, a, b, g, t = head.split()
+            want = [int(s, 2) for s in (a, b, g, t)]
+            for d in map(int, states.split()):
+                j = d // 2
+                got = [lab[2 * j][0], lab[2 * j][1], lab[2 * j + 1][0], lab[2 * j + 1][1]]
+                assert got == want, (d, got, want)
+                seen.add(d)
+    assert seen == set(range(64))
+
+
+@pytest.mark.parametrize("K,gens", ALL_CODES)
+def test_butterfly_and_eq3_to_eq6(K, gens):
+    """Sec. III-B butterfly and the identities of Eq. 3-6 for every j."""
+    N = 1 << (K - 1)
+    nxt, lab = oracle.trellis(K, gens)
+    gK, g0 = gcol(gens, K - 1), gcol(gens, 0)
+    for j in range(N // 2):
+        assert nxt[2 * j][0] == j and nxt[2 * j + 1][0] == j
+        assert nxt[2 * j][1] == j + N // 2 and nxt[2 * j + 1][1] == j + N // 2
+        alpha = lab[2 * j][0]
+        # Eq. 3: alpha is the xor of the columns of the register cells set in S_2j
+        want_alpha = 0
+        for k in range(1, K - 1):
+            if ((2 * j) >> k) & 1:
+                want_alpha ^= gcol(gens, k)
+        assert alpha == want_alpha
+        assert lab[2 * j][1] == alpha ^ gK               # Eq. 4
+        assert lab[2 * j + 1][0] == alpha ^ g0           # Eq. 5
+        assert lab[2 * j + 1][1] == alpha ^ gK ^ g0      # Eq. 6
+
+
+@pytest.mark.parametrize("K,gens", ALL_CODES)
+def test_encoder_impulse_response(K, gens):
+    """A single 1 followed by zeros yields g_{K-1}, g_{K-2}, ..., g_0 (Eq. 2)."""
+    info = np.zeros(K, dtype=np.uint8)
+    info[0] = 1
+    cb = datagen.encode(K, gens, info, terminated=False)
+    for t in range(K):
+        for r, g in enumerate(gens):
+            assert cb[t, r] == (g >> (K - 1 - t)) & 1
+
+
+@pytest.mark.parametrize("K,gens", ALL_CODES)
+def test_trellis_walk_matches_encoder(K, gens):
+    """Walking the oracle's trellis from state 0 reproduces the datagen encoder
+    (two independent formulations of Eq. 2)."""
+    rng = np.random.default_rng(K * 100 + len(gens))
+    info = rng.integers(0, 2, 300, dtype=np.uint8)
+    cb = datagen.encode(K, gens, info, terminated=True)
+    nxt, lab = oracle.trellis(K, gens)
+    R = len(gens)
+    s = 0
+    u = np.concatenate([info, np.zeros(K - 1, dtype=np.uint8)])
+    for t, x in enumerate(u):
+        c = lab[s][x]
+        assert [(c >> (R - 1 - r)) & 1 for r in range(R)] == list(cb[t])
+        s = nxt[s][x]
+    assert s == 0
+
+
+def test_branch_metric_hard_is_hamming():
+    rng = np.random.default_rng(5)
+    for R in (1, 2, 3, 4):
+        bits = rng.integers(0, 2, (200, R), dtype=np.uint8)
+        bm = oracle.branch_metrics(R, bits.reshape(-1), oracle.HARD_U8)
+        for s in range(200):
+            rx = 0
+            for r in range(R):
+                rx = (rx << 1) | int(bits[s, r])
+            for c in range(1 << R):
+                assert bm[s, c] == bin(c ^ rx).count("1")
+
+
+def test_branch_metric_soft_correlation_and_euclidean():
+    """Mismatch metric = (sum|q| - sum x q)/2 with x = 1 - 2c (correlation form),
+    and its differences are 1/(4A) of squared-Euclidean differences."""
+    rng = np.random.default_rng(6)
+    for R in (2, 3, 4):
+        q = rng.integers(-128, 128, (300, R)).astype(np.int8)
+        q[0, :] = -128
+        q[1, :] = 0
+        bm = oracle.branch_metrics(R, q.reshape(-1), oracle.SOFT_I8)
+        qi = q.astype(np.int64)
+        A = 37.0
+        for c in range(1 << R):
+            x = np.array([1 - 2 * ((c >> (R - 1 - r)) & 1) for r in range(R)])
+            corr = (np.abs(qi).sum(1) - (qi * x).sum(1))
+            assert np.all(2 * bm[:, c] == corr)
+            e_c = ((qi - A * x) ** 2).sum(1)
+            x0 = np.ones(R)
+            e_0 = ((qi - A * x0) ** 2).sum(1)
+            assert np.allclose(e_c - e_0, 4 * A * (bm[:, c] - bm[:, 0]))
+    assert bm[0, (1 << R) - 1] == 0 and bm[0, 0] == 128 * R
+
+
+def _spectrum(K, gens, dmax):
+    """Free distance and information-weight spectrum B_d (d <= dmax) of the
+    oracle's trellis: paths leaving state 0 and first returning to it."""
+    nxt, lab = oracle.trellis(K, gens)
+    N = 1 << (K - 1)
+    cnt = {}
+    # frontier[state][w] = (number of paths, total information weight)
+    frontier = {nxt[0][1]: {bin(lab[0][1]).count("1"): (1, 1)}}
+    for _ in range(200):
+        new = {}
+        for s, ws in frontier.items():
+            for x in (0, 1):
+                ns = nxt[s][x]
+                dw = bin(lab[s][x]).count("1")
+                for w, (n_p, iw) in ws.items():
+                    w2 = w + dw
+                    if w2 > dmax:
+                        continue
+                    v = (n_p, iw + x * n_p)
+                    if ns == 0:
+                        a = cnt.get(w2, (0, 0))
+                        cnt[w2] = (a[0] + v[0], a[1] + v[1])
+                    else:
+                        d = new.setdefault(ns, {})
+                        a = d.get(w2, (0, 0))
+                        d[w2] = (a[0] + v[0], a[1] + v[1])
+        frontier = new
+        if not frontier:
+            break
+    assert not frontier, "zero-weight cycle or dmax too large"
+    assert N > 0
+    dfree = min(cnt)
+    return dfree, {d: cnt[d][1] for d in cnt}
+
+
+@pytest.mark.parametrize("K,gens,dfree", [
+    (3, (0o7, 0o5), 5),
+    (7, (0o171, 0o133), 10),
+    (7, (0o133, 0o171, 0o165), 15),
+    (9, (0o557, 0o663, 0o711), 18),
+])
+def test_free_distance(K, gens, dfree):
+    d, _ = _spectrum(K, gens, dfree + 1)
+    assert d == dfree
+
+
+def test_k7_information_weight_spectrum():
+    """Textbook spectrum of the K=7 (171,133) code: B_10, B_12, B_14 = 36, 211, 1404."""
+    d, B = _spectrum(7, (0o171, 0o133), 14)
+    assert d == 10
+    assert B.get(10) == 36 and B.get(11, 0) == 0 and B.get(12) == 211
+    assert B.get(13, 0) == 0 and B.get(14) == 1404
+
+
+def _corr_metric(q, cb):
+    """Path metric of code bits cb[T][R] against soft values q[T][R] in the
+    correlation form (sum|q| - sum x q) / 2, x = 1 - 2c."""
+    x = 1 - 2 * cb.astype(np.int64)
+    qi = q.astype(np.int64)
+    return int((np.abs(qi).sum() - (qi * x).sum()) // 2)
+
+
+@pytest.mark.parametrize("K,gens", [(3, (0o7, 0o5)), (4, (0o15, 0o17)), (5, (0o23, 0o35)),
+                                    (3, (0o5, 0o7, 0o7))])
+@pytest.mark.parametrize("terminated", [True, False])
+def test_bruteforce_maximum_likelihood(K, gens, terminated):
+    """Full-frame oracle = exhaustive search over every input sequence:
+    the decoded sequence has the minimum metric, and every normalized final
+    metric equals the best metric among paths ending in that state."""
+    R = len(gens)
+    N = 1 << (K - 1)
+    for trial in range(4):
+        n = 9
+        st = datagen.make_stream(K, gens, n, 0.5, seed=900 + trial + 10 * K, terminated=terminated)
+        q = st["syms"].view(np.int8).reshape(-1, R)
+        T = st["T"]
+        res = oracle.viterbi_full(K, gens, st["syms"], n, terminated=terminated, want_pm=True)
+        # every input sequence of T stages; the paths ending in state 0 are
+        # exactly the zero-tailed (terminated) ones
+        best = {}
+        for u in itertools.product((0, 1), repeat=T):
+            u = np.array(u, dtype=np.uint8)
+            cb = datagen.encode(K, gens, u, terminated=False)
+            m = _corr_metric(q, cb)
+            end = 0
+            for x in u[-(K - 1):]:
+                end = (int(x) << (K - 2)) | (end >> 1)
+            if end not in best or m < best[end][0]:
+                best[end] = (m, u[:n].copy(), 1)
+            elif m == best[end][0]:
+                best[end] = (m, best[end][1], best[end][2] + 1)
+        gmin = min(v[0] for v in best.values())
+        dec = res["bits"]
+        m_dec = _corr_metric(q, datagen.encode(K, gens, dec, terminated=terminated))
+        target = best[0] if terminated else min(best.values(), key=lambda v: v[0])
+        assert m_dec == target[0]
+        if terminated:
+            assert res["final_pm"][0][0] == best[0][0] - gmin
+        for s in range(N):
+            if s in best:
+                assert res["final_pm"][0][s] == best[s][0] - gmin
+        n_opt = target[2] if terminated else sum(v[2] for v in best.values() if v[0] == gmin)
+        if n_opt == 1:
+            assert np.array_equal(dec, target[1])
+
+
+def test_bruteforce_interior_block_zero_init():
+    """A block that does not start at stage 0 begins from all-zero metrics:
+    its final metrics are the best path metric over every start state."""
+    K, gens = 4, (0o15, 0o17)
+    R, N = 2, 8
+    st = datagen.make_stream(K, gens, 40, 1.0, seed=77, terminated=True)
+    D, L = 4, 3
+    n = 40
+    q = st["syms"].view(np.int8).reshape(-1, R)
+    b = 5
+    f0, f1, d0, d1 = oracle.pb_geometry(n, st["T"], D, L, b)
+    assert (f0, f1) == (17, 27)
+    res = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=b, pb_count=1, want_pm=True)
+    nxt, lab = oracle.trellis(K, gens)
+    best = {}
+    for s0 in range(N):
+        for u in itertools.product((0, 1), repeat=f1 - f0):
+            s = s0
+            cbits = []
+            for x in u:
+                c = lab[s][x]
+                cbits.append([(c >> (R - 1 - r)) & 1 for r in range(R)])
+                s = nxt[s][x]
+            m = _corr_metric(q[f0:f1], np.array(cbits, dtype=np.uint8))
+            best[s] = min(best.get(s, 1 << 60), m)
+    gmin = min(best.values())
+    for s in range(N):
+        assert res["final_pm"][0][s] == best[s] - gmin
+
+
+@pytest.mark.parametrize("K,gens", ALL_CODES[:8])
+@pytest.mark.parametrize("kind", [oracle.SOFT_I8, oracle.HARD_U8])
+def test_noiseless_decodes_exactly(K, gens, kind):
+    n = 1500
+    st = datagen.make_stream(K, gens, n, None, seed=11 * K, kind=kind)
+    full = oracle.viterbi_full(K, gens, st["syms"], n, input_kind=kind, want_pm=True)
+    assert np.array_equal(full["bits"], st["info"])
+    assert full["final_pm"][0][0] == 0
+    blk = oracle.decode(K, gens, 64, 6 * K, st["syms"], n, input_kind=kind)
+    assert np.array_equal(blk["bits"], st["info"])
+
+
+@pytest.mark.parametrize("terminated", [True, False])
+def test_block_equals_full_frame_when_overlap_covers_stream(terminated):
+    K, gens = 5, (0o23, 0o35)
+    n = 300
+    st = datagen.make_stream(K, gens, n, 1.5, seed=31, terminated=terminated)
+    T = st["T"]
+    full = oracle.viterbi_full(K, gens, st["syms"], n, terminated=terminated, want_pm=True)
+    blk = oracle.decode(K, gens, 37, T, st["syms"], n, terminated=terminated, want_pm=True)
+    assert np.array_equal(blk["bits"], full["bits"])
+    for b in range(blk["final_pm"].shape[0]):
+        assert np.array_equal(blk["final_pm"][b], full["final_pm"][0])
+
+
+def test_split_invariance():
+    K, gens = 7, (0o171, 0o133)
+    n = 5000
+    st = datagen.make_stream(K, gens, n, 2.0, seed=41)
+    D, L = 128, 42
+    nb = oracle.num_blocks(n, D)
+    whole = oracle.decode(K, gens, D, L, st["syms"], n, want_pm=True, want_dec=True)
+    parts = [oracle.decode(K, gens, D, L, st["syms"], n, pb_first=a, pb_count=b - a,
+                           want_pm=True, want_dec=True)
+             for a, b in [(0, 7), (7, 8), (8, nb)]]
+    assert np.array_equal(np.concatenate([p["bits"] for p in parts]), whole["bits"])
+    assert np.array_equal(np.concatenate([p["final_pm"] for p in parts]), whole["final_pm"])
+    assert np.array_equal(np.concatenate([p["dec"] for p in parts]), whole["dec"])
+    mt = oracle.decode(K, gens, D, L, st["syms"], n, want_pm=True, nthreads=4)
+    assert np.array_equal(mt["bits"], whole["bits"])
+    assert np.array_equal(mt["final_pm"], whole["final_pm"])
+
+
+def test_block_geometry_cases():
+    """Sec. III-A with M = L, clipped to the stream; workload of 2^20 bits."""
+    n, D, L, K = 1 << 20, 512, 42, 7
+    T = n + K - 1
+    assert oracle.num_blocks(n, D) == 2048
+    assert oracle.pb_geometry(n, T, D, L, 0) == (0, 554, 0, 512)
+    assert oracle.pb_geometry(n, T, D, L, 1) == (470, 1066, 512, 1024)
+    assert oracle.pb_geometry(n, T, D, L, 2047) == (1048022, 1048582, 1048064, 1048576)
+    # decoded ranges tile [0, n) for awkward sizes
+    for n, D, L in [(1, 5, 0), (7, 3, 10), (1000, 1, 0), (999, 64, 42), (4096, 256, 32)]:
+        T = n + 2
+        nb = oracle.num_blocks(n, D)
+        assert nb == math.ceil(n / D)
+        covered = []
+        for b in range(nb):
+            f0, f1, d0, d1 = oracle.pb_geometry(n, T, D, L, b)
+            assert f0 == max(0, b * D - L) and f1 == min(T, b * D + D + L)
+            assert f0 <= d0 < d1 <= f1
+            covered.extend(range(d0, d1))
+        assert covered == list(range(n))
+
+
+def test_decisions_follow_tie_rule():
+    """Equal candidates keep the upper branch: with all-zero soft input every
+    metric ties, so every decision is 0 and the decoded bits are all 0."""
+    K, gens = 7, (0o171, 0o133)
+    n = 700
+    syms = np.zeros((n + K - 1) * 2, dtype=np.uint8)
+    res = oracle.decode(K, gens, 256, 42, syms, n, want_dec=True, want_pm=True)
+    assert not res["dec"].any()
+    assert not res["bits"].any()
+
+
+def test_ber_sanity_k7():
+    """BER of the block decoder (D=512, L=42) at 3 dB: below uncoded BPSK and
+    within a factor of the union bound sum_d B_d Q(sqrt(2 d r Eb/N0))."""
+    K, gens = 7, (0o171, 0o133)
+    n = 1 << 17
+    ebn0 = 3.0
+    st = datagen.make_stream(K, gens, n, ebn0, seed=datagen.config_seed(1, ebn0))
+    res = oracle.decode(K, gens, 512, 42, st["syms"], n, nthreads=8)
+    ber = float(np.mean(res["bits"] != st["info"]))
+    _, B = _spectrum(K, gens, 16)
+    r = 0.5
+    e = 10 ** (ebn0 / 10)
+    bound = sum(Bd * 0.5 * math.erfc(math.sqrt(d * r * e)) for d, Bd in B.items())
+    assert ber < datagen.uncoded_ber(ebn0)
+    assert 0.1 * bound < ber < 3.0 * bound, (ber, bound)
