@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the MI355X parallel block-based Viterbi decoder.
+
+Workload (the plain-decoder throughput run): K=7 rate-1/2 code (171,133),
+a stream of 2^27 random information bits, BPSK/AWGN at Eb/N0 = 3 dB, int8
+soft inputs, D = 512, L = 42 (= 6K), int16 path metrics, zero-terminated.
+One step = one pbvd_decode of the whole stream with inputs and outputs
+resident in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("decoded Mbps, K=7 r1/2 soft, 1 MI355X (batched vs plain); serving p99 latency")
+PEAK_ALU_OPS = {16: 78.6e12, 32: 39.3e12}  # 256 CU x 64 lanes x 2.4 GHz (x2 for packed 16-bit)
+KERNEL_SOURCES = ["paper_1608_00066_amd/csrc/pbvd_kernel.hpp",
+                  "paper_1608_00066_amd/csrc/pbvd_code_inst.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "decode_kernel_k7_d512_2p27_traffic.txt")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def forward_stage_sum(plan, n_bits: int) -> int:
+    geo = plan.block_geometry(n_bits)
+    return int((geo[:, 1] - geo[:, 0]).sum())
+
+
+def time_decode(torch, plan, syms, n_bits, out, steps, warmup):
+    """Warm-up, then `steps` timed decodes.  Returns (ms per step from the
+    host clock between synchronizations, mean kernel ms from HIP events on
+    the stream the decode kernel runs on)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        plan.decode(syms, n_bits, out=out, stream=stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        plan.decode(syms, n_bits, out=out, stream=stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms = sum(s.elapsed_time(e) for s, e in ev) / steps
+    return (t1 - t0) * 1e3 / steps, kernel_ms
+
+
+def cpu_baseline(st, K, gens, D, L, target_s: float):
+    """The CPU oracle on a contiguous sample of the same stream's blocks,
+    using every host core; sample size calibrated to about target_s."""
+    import oracle
+    n = st["n"]
+    threads = os.cpu_count() or 1
+    nb_total = oracle.num_blocks(n, D)
+    probe = min(nb_total, max(64, 8 * threads))
+    t0 = time.perf_counter()
+    oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=probe, nthreads=threads)
+    dt = time.perf_counter() - t0
+    count = int(min(nb_total, max(probe, probe * target_s / max(dt, 1e-3))))
+    t0 = time.perf_counter()
+    res = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=count,
+                        nthreads=threads)
+    dt = time.perf_counter() - t0
+    bits = res["bits"].size
+    return {"value": round(bits / dt / 1e6, 3), "unit": "Mbps", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d of %d parallel blocks (%d decoded bits) of the same stream, "
+                      "%.1f s" % (count, nb_total, bits, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-bits", type=int, default=27)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the secondary K=9 and 2^20-bit measurements")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the decoder has no multi-GPU path in this "
+              "build (PBs shard without communication; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1608_00066_amd import datagen, pbvd
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pbvd.lib()
+    K, gens, D, L, ebn0 = 7, (0o171, 0o133), 512, 42, 3.0
+    n = 1 << args.log2_bits
+    log("generating %d-bit stream" % n)
+    st = datagen.make_stream(K, gens, n, ebn0, datagen.config_seed(2, ebn0, 0))
+    syms = torch.from_numpy(st["syms"]).cuda()
+    out = torch.empty((n + 7) // 8, dtype=torch.uint8, device="cuda")
+    plan = pbvd.Plan(K, gens, D, L, True, datagen.SOFT_I8, 16)
+    log("timing %d steps after %d warm-up" % (args.steps, args.warmup))
+    ms, kernel_ms = time_decode(torch, plan, syms, n, out, args.steps, args.warmup)
+    bits = np.unpackbits(out.cpu().numpy(), bitorder="little")[:n]
+    ber = float(np.mean(bits != st["info"]))
+    acs = forward_stage_sum(plan, n) * (1 << (K - 1))
+    ops = 4.0 * acs  # add, add, compare, select per add-compare-select
+    achieved = ops / (kernel_ms * 1e-3)
+    peak = PEAK_ALU_OPS[16]
+    value = n / (ms * 1e-3) / 1e6
+
+    extras = {"ber": ber, "kernel_ms": round(kernel_ms, 4),
+              "kernel_decoded_mbps": round(n / (kernel_ms * 1e-3) / 1e6, 1),
+              "acs_per_bit": round(acs / n, 2)}
+    if not args.no_extras:
+        for tag, (k2, g2, d2, l2, lb) in {
+                "k9_r3_d512_2p27": (9, (0o557, 0o663, 0o711), 512, 54, args.log2_bits),
+                "k7_r2_d512_2p20": (7, (0o171, 0o133), 512, 42, 20)}.items():
+            n2 = 1 << lb
+            s2 = datagen.make_stream(k2, g2, n2, ebn0, datagen.config_seed(2, ebn0, 1))
+            d_s2 = torch.from_numpy(s2["syms"]).cuda()
+            o2 = torch.empty((n2 + 7) // 8, dtype=torch.uint8, device="cuda")
+            with pbvd.Plan(k2, g2, d2, l2, True, datagen.SOFT_I8, 16) as p2:
+                ms2, kms2 = time_decode(torch, p2, d_s2, n2, o2, max(3, args.steps // 4), 2)
+            extras[tag + "_mbps"] = round(n2 / (ms2 * 1e-3) / 1e6, 1)
+            del d_s2, o2, s2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(st, K, gens, D, L, args.cpu_seconds)
+
+    rec = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "Mbps",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int16",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain PBVD throughput run: K=7 r1/2 (171,133), 2^%d info bits, "
+                        "int8 soft at Eb/N0=3 dB, D=512, L=42, int16 path metrics, "
+                        "zero-terminated" % args.log2_bits,
+            "n_bits": n, "K": K, "R": 2, "D": D, "L": L, "parallel_blocks": plan.num_blocks(n),
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": round(achieved / 1e12, 3),
+            "peak": peak / 1e12,
+            "unit": "Tops/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(),
+        },
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    plan.close()
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

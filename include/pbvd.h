@@ -1,0 +1,161 @@
+/*
+ * pbvd.h -- C ABI of the MI355X parallel block-based Viterbi decoder.
+ *
+ * The decoder implements the parallel block-based Viterbi decoder (PBVD) of
+ * Peng, Liu, Hou and Zhao, "A Gb/s Parallel Block-based Viterbi Decoder for
+ * Convolutional Codes on GPU" (arXiv 1608.00066):
+ *   - the problem (Sec. II, Sec. III-A): a stream of rate-1/R, constraint
+ *     length K convolutional-code symbols received over AWGN is decoded into
+ *     its information bits;
+ *   - the block decomposition (Sec. III-A, Fig. 1 and 2, M = L): the stream
+ *     is cut into parallel blocks (PBs) of D decoded bits, each extended by L
+ *     stages on both sides; PBs are decoded independently;
+ *   - per PB, a forward add-compare-select pass (Eq. 1) over the 2^(K-1)
+ *     states with branch metrics shared per butterfly group (Eq. 2-6) and
+ *     bit-packed survivor decisions (Sec. IV-B), then a traceback from a fixed
+ *     start state that emits the D decoded bits (Alg. 1, Kernel 2), packed
+ *     eight per byte (Sec. IV-C).
+ *
+ * Conventions fixed by this library where the paper is silent:
+ *   - gen[r] bit k is g_k^(r) of Eq. 2 (octal 171 = 1111001); bit K-1 taps
+ *     the current input bit; state d = (D_{K-2} ... D_0)_2 with D_{K-2} the
+ *     newest input (the butterfly of Sec. III-B);
+ *   - the R symbols of one stage are stored consecutively in generator order;
+ *   - soft input: one int8 per symbol, q >= 0 reads as code bit 0, |q| is the
+ *     cost of disagreeing with it; hard input: one byte per symbol, bit =
+ *     byte & 1 (Hamming distance);
+ *   - ties in add-compare-select keep the branch from S_2j;
+ *   - a PB whose forward range starts at stage 0 starts from the known
+ *     encoder state 0; every other PB starts from all-zero metrics (Sec.
+ *     III-A);
+ *   - traceback starts from state 0 (Sec. III-A, Alg. 1); at the end of an
+ *     unterminated stream it starts from the state of least metric (lowest
+ *     index on ties), as full-frame Viterbi does (Sec. II);
+ *   - PB b covers forward stages [max(0, bD-L), min(T, bD+D+L)) and decodes
+ *     bits [bD, min(n, bD+D)); T = n + (K-1) if the stream is terminated
+ *     with K-1 zero bits, else T = n; there are ceil(n/D) PBs;
+ *   - decoded bit i is bit (i & 7) of byte (i >> 3) (least significant bit
+ *     first); unused high bits of the last byte are written as 0.
+ *
+ * Memory: every pointer named d_* is a device (HBM) pointer owned by the
+ * caller.  The plan owns its own device workspace (survivor buffers), which
+ * it allocates and grows on demand during decode and frees in pbvd_destroy.
+ *
+ * Concurrency: decode calls are asynchronous on the given HIP stream (NULL =
+ * the null stream).  A plan holds one workspace: do not run two decodes of
+ * the same plan concurrently (use one plan per stream).
+ *
+ * Errors: arguments are validated before anything is launched; on a
+ * negative status nothing has been written to the output buffers.  No C++
+ * exception crosses this interface.  pbvd_last_error() gives a
+ * human-readable detail of the last failure of the calling thread.
+ */
+#ifndef PBVD_H
+#define PBVD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pbvd_plan pbvd_plan;
+
+typedef enum {
+    PBVD_OK = 0,
+    PBVD_EINVAL = -1,   /* invalid argument */
+    PBVD_ENOTSUP = -2,  /* valid code, but no kernel compiled for it */
+    PBVD_ENOMEM = -3,   /* device workspace allocation failed */
+    PBVD_EHIP = -4      /* HIP runtime error (detail in pbvd_last_error) */
+} pbvd_status;
+
+enum {
+    PBVD_SOFT_I8 = 0,   /* int8 soft value per code symbol */
+    PBVD_HARD_U8 = 1    /* uint8 per code symbol, bit = byte & 1 */
+};
+
+/* Code and block parameters (Sec. III-A, Sec. III-B). */
+typedef struct {
+    int32_t K;          /* constraint length, 3..9 (N = 2^(K-1) states) */
+    int32_t R;          /* 1/R code rate, 2..4 */
+    uint32_t gen[4];    /* generators gen[0..R-1] (bit k = g_k); at least one
+                           has bit K-1 set; all < 2^K */
+    int32_t D;          /* decoded bits per PB, >= 1 */
+    int32_t L;          /* overlap on each side (M = L), >= 0; D + 2L < 2^30 */
+    int32_t terminated; /* 1: the stream carries K-1 zero tail stages after n */
+    int32_t input_kind; /* PBVD_SOFT_I8 or PBVD_HARD_U8 */
+    int32_t pm_bits;    /* path-metric width, 16 or 32 (32 needs K <= 8);
+                           results are identical, only the kernel differs */
+} pbvd_code;
+
+/* Validate `code`, build the trellis tables and pick the kernel.
+ * *out receives a new plan (no device memory is allocated yet).
+ * Returns PBVD_EINVAL for out-of-range fields, PBVD_ENOTSUP when no kernel
+ * is compiled for this generator set / metric width. */
+pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out);
+
+/* Decode a whole stream.
+ *   d_syms     : device, (n_bits + terminated*(K-1)) * R bytes, stage-major
+ *   n_bits     : information bits, >= 1
+ *   d_out_bits : device, ceil(n_bits/8) bytes, written completely
+ *   hip_stream : hipStream_t or NULL
+ * Asynchronous; equivalent to pbvd_decode_ex over all PBs. */
+pbvd_status pbvd_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, uint8_t *d_out_bits,
+                        void *hip_stream);
+
+/* Decode PBs [pb_first, pb_first + pb_count) of a stream of n_bits bits
+ * (resume, sharding, verification).
+ *   d_out_bits : device, receives decoded bits [pb_first*D, min(n, (pb_first
+ *                + pb_count)*D)) of the stream starting at its bit 0;
+ *                ceil(that count / 8) bytes, written completely
+ *   d_final_pm : device int32 [pb_count][2^(K-1)] or NULL: path metrics at the
+ *                end of each PB's forward range minus their minimum
+ * pb_count may be 0 (nothing is written).  Asynchronous. */
+pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                           int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
+                           void *hip_stream);
+
+/* Number of parallel blocks of a stream: ceil(n_bits / D); 0 if n_bits < 1. */
+int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits);
+
+/* Host-side block geometry (Sec. III-A): for PBs [pb_first, pb_first +
+ * pb_count) of a stream of n_bits bits writes 4 values per PB to the host
+ * array out: forward range start f0, end f1, decoded range start d0, end d1.
+ * Returns PBVD_EINVAL for a range outside [0, pbvd_num_blocks). */
+pbvd_status pbvd_block_geometry(const pbvd_plan *p, int64_t n_bits, int64_t pb_first,
+                                int64_t pb_count, int64_t *out);
+
+/* Verification hook for the survivor layout: decodes PBs [pb_first,
+ * pb_first + pb_count) like pbvd_decode_ex and then expands the packed
+ * survivor decisions they stored into d_dec, a device uint8 array
+ * [pb_count][D+L][2^(K-1)]: row s - b*D holds the decision (1 = lower
+ * branch, from S_2j+1) of every state at stage s for s in [b*D, f1); other
+ * rows are zero.  d_out_bits as in pbvd_decode_ex.  Synchronizes the stream.
+ * Returns PBVD_EINVAL when the range does not fit the workspace of a single
+ * launch. */
+pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bits,
+                                 int64_t pb_first, int64_t pb_count, uint8_t *d_out_bits,
+                                 uint8_t *d_dec, void *hip_stream);
+
+/* Verification hook for the branch metrics: for stages [0, n_stages) of
+ * d_syms writes the 2^R code-word metrics the forward kernel computes into
+ * the device int32 array d_bm [n_stages][2^R] (code word c has c^(1) as its
+ * most significant bit).  These equal the Sec. II distances minus a
+ * per-stage constant shared by all code words.  Asynchronous. */
+pbvd_status pbvd_debug_branch_metrics(pbvd_plan *p, const void *d_syms, int64_t n_stages,
+                                      int32_t *d_bm, void *hip_stream);
+
+/* Free the plan and its device workspace (synchronizes the device). */
+void pbvd_destroy(pbvd_plan *p);
+
+/* Static description of a status code. */
+const char *pbvd_strerror(pbvd_status s);
+
+/* Detail of the last failed call on this thread ("" if none). */
+const char *pbvd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PBVD_H */

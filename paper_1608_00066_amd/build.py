@@ -1,0 +1,74 @@
+"""Build ``libpbvd.so`` (HIP kernels for gfx950 + the C ABI) in-tree.
+
+Every translation unit is compiled with hipcc for gfx950 only; the per-code
+kernel unit is compiled once per registered code so the builds run in
+parallel.  Usage: ``python -m paper_1608_00066_amd.build`` or ``build()``.
+"""
+from __future__ import annotations
+
+import os
+import re
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+BUILD_DIR = os.path.join(PKG, "_build")
+LIB = os.path.join(PKG, "libpbvd.so")
+ARCH = "gfx950"
+
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+# -packed-fp32-ops: keep hipcc from forming packed fp32 instructions
+COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-I", INCLUDE, "-I", CSRC]
+
+
+def num_codes() -> int:
+    with open(os.path.join(CSRC, "pbvd_registry.hpp")) as f:
+        return len(re.findall(r"^\s*X\(\d+,", f.read(), flags=re.M))
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(line for line in r.stdout.splitlines()
+                    if "packed-fp32-ops" not in line)
+    if r.returncode != 0:
+        raise RuntimeError("command failed (%d): %s\n%s" % (r.returncode, " ".join(cmd), out))
+    return out
+
+
+def build(jobs: int | None = None, verbose: bool = False) -> str:
+    """Compile every unit and link ``libpbvd.so``; returns its path."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    jobs = jobs or min(16, os.cpu_count() or 4)
+    units = []
+    for i in range(num_codes()):
+        units.append((os.path.join(CSRC, "pbvd_code_inst.hip"),
+                      os.path.join(BUILD_DIR, "code_%02d.o" % i), ["-DPBVD_CODE_IDX=%d" % i]))
+    for name in ("pbvd_capi", "pbvd_aux"):
+        units.append((os.path.join(CSRC, name + ".hip"), os.path.join(BUILD_DIR, name + ".o"), []))
+
+    def compile_unit(u):
+        src, obj, extra = u
+        _run([HIPCC, *COMMON, *extra, "-c", src, "-o", obj])
+        if verbose:
+            print("built", os.path.basename(obj), flush=True)
+        return obj
+
+    # longest units first (K=9 kernels)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_unit, sorted(units, key=lambda u: u[1])))
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *sorted(objs)])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    path = build(verbose="-v" in sys.argv)
+    print(path)

@@ -1,0 +1,407 @@
+// C ABI of the decoder (declared in include/pbvd.h): argument validation,
+// plan and workspace management, the block decomposition of a call into
+// kernel launches, and error reporting.  No C++ exception leaves this file.
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "pbvd.h"
+#include "pbvd_aux.hpp"
+#include "pbvd_registry.hpp"
+
+#define PBVD_ROW(i, K, R, g0, g1, g2, g3) {K, R, {g0, g1, g2, g3}},
+const RegisteredCode kRegisteredCodes[kNumCodes] = {PBVD_CODE_LIST(PBVD_ROW)};
+#undef PBVD_ROW
+
+namespace {
+
+using LaunchFn = hipError_t (*)(const pbvd::LaunchRequest &);
+#define PBVD_FN(i, K, R, g0, g1, g2, g3) &pbvd::launch_code<i>,
+const LaunchFn kLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_FN)};
+#undef PBVD_FN
+
+thread_local char g_last_error[512];
+
+pbvd_status fail(pbvd_status s, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof(g_last_error), fmt, ap);
+    va_end(ap);
+    return s;
+}
+
+pbvd_status fail_hip(hipError_t e, const char *what) {
+    return fail(PBVD_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Block decomposition of one call (Sec. III-A with M = L): PBs with the full
+// forward range [bD-L, bD+D+L) and decoded range [bD, bD+D) are "interior"
+// and go 64 to a wave; the others (stream ends) get a wave each.
+struct CallGeometry {
+    int64_t T, pb_first, pb_end;
+    int64_t b_lo, b_hi, n_head, n_tail;
+    int64_t n_int_waves, n_waves;
+    int64_t out_bits;
+};
+
+CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int64_t pb_count) {
+    CallGeometry g{};
+    const int64_t D = c.D, L = c.L;
+    g.T = n + (c.terminated ? c.K - 1 : 0);
+    g.pb_first = pb_first;
+    g.pb_end = pb_first + pb_count;
+    int64_t lo = ceil_div(L, D);
+    if (lo < pb_first) lo = pb_first;
+    const int64_t lim = (g.T - D - L) < (n - D) ? (g.T - D - L) : (n - D);
+    int64_t hi = lim < 0 ? 0 : lim / D + 1;
+    if (hi > g.pb_end) hi = g.pb_end;
+    if (lo < hi) {
+        g.b_lo = lo;
+        g.b_hi = hi;
+        g.n_head = lo - pb_first;
+        g.n_tail = g.pb_end - hi;
+        g.n_int_waves = ceil_div(hi - lo, pbvd::kWave);
+    } else {
+        g.b_lo = g.b_hi = g.pb_end;
+        g.n_head = pb_count;
+        g.n_tail = 0;
+        g.n_int_waves = 0;
+    }
+    g.n_waves = g.n_int_waves + g.n_head + g.n_tail;
+    const int64_t end_bit = g.pb_end * D < n ? g.pb_end * D : n;
+    g.out_bits = pb_count > 0 ? end_bit - pb_first * D : 0;
+    return g;
+}
+
+int find_code(const pbvd_code &c) {
+    for (int i = 0; i < kNumCodes; ++i) {
+        const RegisteredCode &r = kRegisteredCodes[i];
+        if (r.K != c.K || r.R != c.R) continue;
+        bool same = true;
+        for (int k = 0; k < c.R; ++k) same = same && r.gen[k] == c.gen[k];
+        if (same) return i;
+    }
+    return -1;
+}
+
+bool fault_injected(const char *site) {
+    const char *f = getenv("PBVD_FAULT_INJECT");
+    return f && strcmp(f, site) == 0;
+}
+
+}  // namespace
+
+struct pbvd_plan {
+    pbvd_code code;
+    int code_idx;
+    int device;
+    int ndw;                  // survivor dwords per stored row
+    int row_stages;           // stages per stored row
+    int64_t sp_wave_dwords;   // survivor dwords per wave slot
+    int64_t budget_bytes;     // survivor workspace limit
+    uint32_t *sp;
+    size_t sp_bytes;
+    uint32_t *words;
+    size_t words_bytes;
+};
+
+namespace {
+
+// Makes the plan's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            ok = false;
+            return;
+        }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char *what) {
+    if (*have >= need) return PBVD_OK;
+    if (*buf) {
+        hipError_t e = hipFree(*buf);
+        *buf = nullptr;
+        *have = 0;
+        if (e != hipSuccess) return fail_hip(e, "hipFree");
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(PBVD_ENOMEM, "hipMalloc of %zu bytes for %s failed: %s", need, what,
+                    hipGetErrorString(e));
+    }
+    *buf = (uint32_t *)p;
+    *have = need;
+    return PBVD_OK;
+}
+
+int64_t waves_per_launch(const pbvd_plan *p) {
+    int64_t w = p->budget_bytes / (p->sp_wave_dwords * 4);
+    return w < 1 ? 1 : w;
+}
+
+pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                          int64_t pb_count, const uint8_t *d_out) {
+    if (!p) return fail(PBVD_EINVAL, "plan is NULL");
+    if (!d_syms) return fail(PBVD_EINVAL, "d_syms is NULL");
+    if (n_bits < 1) return fail(PBVD_EINVAL, "n_bits must be >= 1 (got %lld)", (long long)n_bits);
+    const int64_t nb = ceil_div(n_bits, p->code.D);
+    if (pb_first < 0 || pb_count < 0 || pb_first > nb || pb_count > nb - pb_first)
+        return fail(PBVD_EINVAL, "PB range [%lld, %lld) outside [0, %lld)", (long long)pb_first,
+                    (long long)(pb_first + pb_count), (long long)nb);
+    if (pb_count > 0 && !d_out) return fail(PBVD_EINVAL, "d_out_bits is NULL");
+    return PBVD_OK;
+}
+
+// Runs the decode kernels of one call; fills *geo with the decomposition.
+pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                       int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm, hipStream_t stream,
+                       CallGeometry *geo_out, bool single_launch) {
+    const pbvd_code &c = p->code;
+    const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count);
+    if (geo_out) *geo_out = g;
+    if (pb_count == 0) return PBVD_OK;
+    const int64_t per_launch = waves_per_launch(p);
+    if (single_launch && g.n_waves > per_launch)
+        return fail(PBVD_EINVAL, "%lld waves do not fit one launch (limit %lld)",
+                    (long long)g.n_waves, (long long)per_launch);
+    if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
+
+    const int64_t launch_waves = g.n_waves < per_launch ? g.n_waves : per_launch;
+    pbvd_status st = ensure_buffer(&p->sp, &p->sp_bytes,
+                                   (size_t)(launch_waves * p->sp_wave_dwords * 4), "survivors");
+    if (st != PBVD_OK) return st;
+
+    const int64_t out_bytes = ceil_div(g.out_bits, 8);
+    const bool direct = (c.D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
+    if (!direct) {
+        const int64_t nwords = ceil_div(g.out_bits, 32) + 2;
+        st = ensure_buffer(&p->words, &p->words_bytes, (size_t)nwords * 4, "output staging");
+        if (st != PBVD_OK) return st;
+        hipError_t e = pbvd::fill_u32(p->words, nwords, 0u, stream);
+        if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
+    }
+
+    pbvd::LaunchRequest req{};
+    pbvd::KernelArgs &a = req.args;
+    a.syms = (const uint8_t *)d_syms;
+    a.out = d_out;
+    a.out_words = direct ? nullptr : p->words;
+    a.final_pm = d_final_pm;
+    a.sp = p->sp;
+    a.n = n_bits;
+    a.T = g.T;
+    a.pb_first = pb_first;
+    a.b_lo = g.b_lo;
+    a.b_hi = g.b_hi;
+    a.n_head = g.n_head;
+    a.n_int_waves = g.n_int_waves;
+    a.out_bytes = out_bytes;
+    a.sp_wave_dwords = p->sp_wave_dwords;
+    a.D = c.D;
+    a.L = c.L;
+    a.terminated = c.terminated;
+    a.direct_out = direct ? 1 : 0;
+    req.pm_bits = c.pm_bits;
+    req.input_kind = c.input_kind;
+    req.stream = stream;
+    const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
+    for (int64_t w0 = 0; w0 < g.n_waves; w0 += launch_waves) {
+        a.wave_begin = w0;
+        a.n_waves = (g.n_waves - w0) < launch_waves ? (g.n_waves - w0) : launch_waves;
+        req.grid = (unsigned)ceil_div(a.n_waves, waves_per_block);
+        hipError_t e = kLaunchTable[p->code_idx](req);
+        if (e != hipSuccess) return fail_hip(e, "decode kernel launch");
+    }
+    if (!direct) {
+        hipError_t e = pbvd::words_to_bytes(p->words, d_out, out_bytes, stream);
+        if (e != hipSuccess) return fail_hip(e, "output copy launch");
+    }
+    return PBVD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
+    g_last_error[0] = 0;
+    if (!code || !out) return fail(PBVD_EINVAL, "code and out must not be NULL");
+    const pbvd_code &c = *code;
+    if (c.K < 3 || c.K > 9) return fail(PBVD_EINVAL, "K must be in [3, 9] (got %d)", c.K);
+    if (c.R < 2 || c.R > 4) return fail(PBVD_EINVAL, "R must be in [2, 4] (got %d)", c.R);
+    bool taps_input = false;
+    for (int r = 0; r < c.R; ++r) {
+        if (c.gen[r] >> c.K) return fail(PBVD_EINVAL, "generator %d (0%o) has bits above K-1", r, c.gen[r]);
+        if (c.gen[r] == 0) return fail(PBVD_EINVAL, "generator %d is zero", r);
+        taps_input = taps_input || ((c.gen[r] >> (c.K - 1)) & 1u);
+    }
+    if (!taps_input) return fail(PBVD_EINVAL, "no generator has bit K-1 set: constraint length is below K");
+    if (c.D < 1) return fail(PBVD_EINVAL, "D must be >= 1 (got %d)", c.D);
+    if (c.L < 0) return fail(PBVD_EINVAL, "L must be >= 0 (got %d)", c.L);
+    if ((int64_t)c.D + 2 * (int64_t)c.L >= (1LL << 30)) return fail(PBVD_EINVAL, "D + 2L must be below 2^30");
+    if (c.terminated != 0 && c.terminated != 1) return fail(PBVD_EINVAL, "terminated must be 0 or 1");
+    if (c.input_kind != PBVD_SOFT_I8 && c.input_kind != PBVD_HARD_U8)
+        return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
+    if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
+    if (c.pm_bits == 32 && c.K > 8) return fail(PBVD_ENOTSUP, "32-bit path metrics need K <= 8");
+    const int idx = find_code(c);
+    if (idx < 0) return fail(PBVD_ENOTSUP, "no kernel compiled for this generator set");
+
+    pbvd_plan *p = new (std::nothrow) pbvd_plan();
+    if (!p) return fail(PBVD_ENOMEM, "host allocation failed");
+    p->code = c;
+    for (int r = c.R; r < 4; ++r) p->code.gen[r] = 0;
+    p->code_idx = idx;
+    if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+    (void)hipGetLastError();
+    p->ndw = pbvd::survivor_row_dwords(c.K);
+    p->row_stages = pbvd::survivor_row_stages(c.K);
+    const int64_t rows = ceil_div((int64_t)c.D + c.L, p->row_stages) + 1;
+    p->sp_wave_dwords = ceil_div(rows * pbvd::kWave * p->ndw, 64) * 64;
+    int64_t mb = 8192;
+    if (const char *env = getenv("PBVD_WORKSPACE_MB")) {
+        long long v = atoll(env);
+        if (v > 0) mb = v;
+    }
+    p->budget_bytes = mb << 20;
+    *out = p;
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                           int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
+                           void *hip_stream) {
+    g_last_error[0] = 0;
+    pbvd_status st = validate_call(p, d_syms, n_bits, pb_first, pb_count, d_out_bits);
+    if (st != PBVD_OK || pb_count == 0) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
+    return run_decode(p, d_syms, n_bits, pb_first, pb_count, d_out_bits, d_final_pm,
+                      (hipStream_t)hip_stream, nullptr, false);
+}
+
+pbvd_status pbvd_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, uint8_t *d_out_bits,
+                        void *hip_stream) {
+    if (!p) return fail(PBVD_EINVAL, "plan is NULL");
+    if (n_bits < 1) return fail(PBVD_EINVAL, "n_bits must be >= 1 (got %lld)", (long long)n_bits);
+    return pbvd_decode_ex(p, d_syms, n_bits, 0, ceil_div(n_bits, p->code.D), d_out_bits, nullptr,
+                          hip_stream);
+}
+
+int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits) {
+    if (!p || n_bits < 1) return 0;
+    return ceil_div(n_bits, p->code.D);
+}
+
+pbvd_status pbvd_block_geometry(const pbvd_plan *p, int64_t n_bits, int64_t pb_first,
+                                int64_t pb_count, int64_t *out) {
+    g_last_error[0] = 0;
+    if (!p) return fail(PBVD_EINVAL, "plan is NULL");
+    if (n_bits < 1) return fail(PBVD_EINVAL, "n_bits must be >= 1");
+    const int64_t nb = ceil_div(n_bits, p->code.D);
+    if (pb_first < 0 || pb_count < 0 || pb_first > nb || pb_count > nb - pb_first)
+        return fail(PBVD_EINVAL, "PB range outside [0, %lld)", (long long)nb);
+    if (pb_count > 0 && !out) return fail(PBVD_EINVAL, "out is NULL");
+    const int64_t D = p->code.D, L = p->code.L;
+    const int64_t T = n_bits + (p->code.terminated ? p->code.K - 1 : 0);
+    for (int64_t i = 0; i < pb_count; ++i) {
+        const int64_t d0 = (pb_first + i) * D;
+        out[4 * i + 0] = d0 - L < 0 ? 0 : d0 - L;
+        out[4 * i + 1] = d0 + D + L > T ? T : d0 + D + L;
+        out[4 * i + 2] = d0;
+        out[4 * i + 3] = d0 + D > n_bits ? n_bits : d0 + D;
+    }
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bits,
+                                 int64_t pb_first, int64_t pb_count, uint8_t *d_out_bits,
+                                 uint8_t *d_dec, void *hip_stream) {
+    g_last_error[0] = 0;
+    pbvd_status st = validate_call(p, d_syms, n_bits, pb_first, pb_count, d_out_bits);
+    if (st != PBVD_OK) return st;
+    if (pb_count > 0 && !d_dec) return fail(PBVD_EINVAL, "d_dec is NULL");
+    if (pb_count == 0) return PBVD_OK;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    CallGeometry g{};
+    st = run_decode(p, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true);
+    if (st != PBVD_OK || pb_count == 0) return st;
+    pbvd::SurvivorView v{};
+    v.sp = p->sp;
+    v.sp_wave_dwords = p->sp_wave_dwords;
+    v.T = g.T;
+    v.pb_first = pb_first;
+    v.pb_count = pb_count;
+    v.b_lo = g.b_lo;
+    v.b_hi = g.b_hi;
+    v.n_head = g.n_head;
+    v.n_int_waves = g.n_int_waves;
+    v.K = p->code.K;
+    v.D = p->code.D;
+    v.L = p->code.L;
+    hipError_t e = pbvd::unpack_survivors(v, d_dec, s);
+    if (e != hipSuccess) return fail_hip(e, "survivor expansion launch");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_debug_branch_metrics(pbvd_plan *p, const void *d_syms, int64_t n_stages,
+                                      int32_t *d_bm, void *hip_stream) {
+    g_last_error[0] = 0;
+    if (!p) return fail(PBVD_EINVAL, "plan is NULL");
+    if (n_stages < 0) return fail(PBVD_EINVAL, "n_stages must be >= 0");
+    if (n_stages > 0 && (!d_syms || !d_bm)) return fail(PBVD_EINVAL, "NULL buffer");
+    if (n_stages == 0) return PBVD_OK;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
+    hipError_t e = pbvd::branch_metrics(p->code.R, p->code.input_kind, (const uint8_t *)d_syms,
+                                        n_stages, d_bm, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail_hip(e, "branch-metric launch");
+    return PBVD_OK;
+}
+
+void pbvd_destroy(pbvd_plan *p) {
+    if (!p) return;
+    {
+        DeviceGuard dg(p->device);
+        if (p->sp || p->words) (void)hipDeviceSynchronize();
+        if (p->sp) (void)hipFree(p->sp);
+        if (p->words) (void)hipFree(p->words);
+    }
+    delete p;
+}
+
+const char *pbvd_strerror(pbvd_status s) {
+    switch (s) {
+    case PBVD_OK: return "success";
+    case PBVD_EINVAL: return "invalid argument";
+    case PBVD_ENOTSUP: return "not supported";
+    case PBVD_ENOMEM: return "out of device memory";
+    case PBVD_EHIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+const char *pbvd_last_error(void) { return g_last_error; }
+
+}  // extern "C"

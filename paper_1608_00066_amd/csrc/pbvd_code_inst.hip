@@ -1,0 +1,48 @@
+// Decoder kernels of one registered code.  Compiled once per code with
+// -DPBVD_CODE_IDX=<index>, so the per-code kernels build in parallel.
+#include "pbvd_registry.hpp"
+
+#ifndef PBVD_CODE_IDX
+#error "compile with -DPBVD_CODE_IDX=<registry index>"
+#endif
+
+namespace pbvd {
+namespace {
+
+template <int IDX>
+struct CodeAt;
+#define PBVD_CODE_AT(i, K, R, g0, g1, g2, g3) \
+    template <>                               \
+    struct CodeAt<i> {                        \
+        using type = FixedCode<K, R, g0, g1, g2, g3>; \
+    };
+PBVD_CODE_LIST(PBVD_CODE_AT)
+#undef PBVD_CODE_AT
+
+template <class C, class P, int KIND>
+hipError_t launch_one(const LaunchRequest &req) {
+    hipLaunchKernelGGL((decode_kernel<C, P, KIND>), dim3(req.grid), dim3(kBlockThreads), 0,
+                       req.stream, req.args);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <int IDX>
+hipError_t launch_code(const LaunchRequest &req) {
+    using C = typename CodeAt<IDX>::type;
+    if (req.pm_bits == 16) {
+        return req.input_kind == kHardU8 ? launch_one<C, PM16, kHardU8>(req)
+                                         : launch_one<C, PM16, kSoftI8>(req);
+    }
+    if constexpr (C::K <= 8) {
+        if (req.pm_bits == 32)
+            return req.input_kind == kHardU8 ? launch_one<C, PM32, kHardU8>(req)
+                                             : launch_one<C, PM32, kSoftI8>(req);
+    }
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_code<PBVD_CODE_IDX>(const LaunchRequest &req);
+
+}  // namespace pbvd

@@ -1,0 +1,482 @@
+// Forward add-compare-select, survivor packing and traceback of the parallel
+// block-based Viterbi decoder (arXiv 1608.00066, Sec. III-A), written for
+// gfx950 wave64.
+//
+// Mapping: one lane decodes one parallel block (PB); one wave decodes 64 PBs
+// that share a geometry, so every loop bound, phase and branch below is
+// wave-uniform.  All N = 2^(K-1) path metrics of a lane live in VGPRs as
+// N/2 packed pairs; the butterfly of Sec. III-B is done in place, which
+// rotates the state <-> register assignment by one bit per stage and brings
+// it back to the identity after K-1 stages (the unroll length).
+//
+// State <-> register map at phase ph (ph = stage index mod (K-1)):
+//   u = rotl_{K-1}(state, ph); register = u mod N/2; half = u >> (K-2).
+// A stage at phase ph < K-2 pairs register X (bit ph clear) with
+// Y = X | 2^ph: X holds the even predecessors S_2j, Y the odd ones S_2j+1;
+// the two new metrics for input 0 go back into X, those for input 1 into Y.
+// At phase K-2 a register holds S_2j and S_2j+1 itself and is updated with
+// half-broadcast operands.
+//
+// Branch metrics: only the 2^R distinct code-word metrics of a stage are
+// computed (Sec. III-B, Eq. 3-6: every branch of a butterfly is alpha,
+// beta, gamma or theta).  They are taken as sum_{r: c_r = 1} q_r, which
+// differs from the mismatch distance by a constant shared by all code words
+// of the stage; decisions and metric differences are therefore unchanged.
+//
+// Survivors: one bit per state and stage, 1 = lower branch (Sec. IV-B);
+// bit position = register slot (+16 for the upper half of the pair).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace pbvd {
+
+constexpr int kWave = 64;
+
+// Compile-time loop: f(std::integral_constant<int, I>) for I in [B, E), until
+// f returns false.  Returns false if it stopped early.
+template <int B, int E, class F>
+__device__ __forceinline__ bool static_for(F &&f) {
+    if constexpr (B < E) {
+        if (!f(std::integral_constant<int, B>{})) return false;
+        return static_for<B + 1, E>(f);
+    } else {
+        return true;
+    }
+}
+
+struct KernelArgs {
+    const uint8_t *syms;    // T*R received symbols, stage-major
+    uint8_t *out;           // packed decoded bits (direct path)
+    uint32_t *out_words;    // zeroed word buffer (atomic path) or null
+    int32_t *final_pm;      // [pb_count][N] normalized final metrics or null
+    uint32_t *sp;           // survivor scratch, sp_wave_dwords per wave slot
+    int64_t n;              // information bits of the stream
+    int64_t T;              // trellis stages (n + K-1 when terminated)
+    int64_t pb_first;       // first PB of this call
+    int64_t b_lo, b_hi;     // interior PBs (full geometry) of this call
+    int64_t n_head;         // edge PBs [pb_first, pb_first + n_head) precede b_lo
+    int64_t n_int_waves;    // waves covering [b_lo, b_hi), 64 PBs each
+    int64_t wave_begin;     // first wave (interior waves first, then edge waves)
+    int64_t n_waves;        // waves in this launch
+    int64_t out_bytes;      // bytes of `out`
+    int64_t sp_wave_dwords; // survivor dwords per wave slot
+    int32_t D, L;
+    int32_t terminated;
+    int32_t direct_out;     // 1: plain stores into out, 0: atomic OR into out_words
+};
+
+// ---------------------------------------------------------------------------
+// Code description (compile-time generators)
+// ---------------------------------------------------------------------------
+template <int K_, int R_, uint32_t G0, uint32_t G1, uint32_t G2 = 0, uint32_t G3 = 0>
+struct FixedCode {
+    static constexpr int K = K_;
+    static constexpr int R = R_;
+    static constexpr int V = K - 1;       // memory cells
+    static constexpr int N = 1 << V;      // states
+    static constexpr int NR = N / 2;      // packed registers
+    static constexpr int NC = 1 << R;     // code words
+    static constexpr uint32_t gen(int r) { return r == 0 ? G0 : r == 1 ? G1 : r == 2 ? G2 : G3; }
+    // Code word (c^(1) as MSB) contributed by register bit k (k = K-1: input).
+    static constexpr int gcol(int k) {
+        int c = 0;
+        for (int r = 0; r < R; ++r) c = (c << 1) | (int)((gen(r) >> k) & 1u);
+        return c;
+    }
+    // Encoder output c(S_d, 0) of Eq. 2.
+    static constexpr int out0(int d) {
+        int c = 0;
+        for (int k = 0; k < V; ++k)
+            if ((d >> k) & 1) c ^= gcol(k);
+        return c;
+    }
+};
+
+template <int V>
+__host__ __device__ constexpr int rotr_v(int u, int s) {
+    return s == 0 ? u : (((u >> s) | (u << (V - s))) & ((1 << V) - 1));
+}
+template <int V>
+__host__ __device__ constexpr int rotl_v(int u, int s) {
+    return rotr_v<V>(u, (V - s) % V);
+}
+
+// Bit position, inside the survivor word group of one stage, of the
+// decision of the state whose rotated index is u.  Inverse-free: maps u's
+// bit t to bit pos_of_ubit(t).
+template <int V>
+__host__ __device__ constexpr int pos_of_ubit(int t) {
+    return t == V - 1 ? 4 : (t < 4 ? t : t + 1);
+}
+template <int V>
+__device__ __forceinline__ uint32_t u_to_idx(uint32_t u) {
+    constexpr int lowbits = (V - 1) < 4 ? (V - 1) : 4;
+    uint32_t low = u & ((1u << lowbits) - 1u);
+    uint32_t half = (u >> (V - 1)) & 1u;
+    uint32_t idx = low | (half << 4);
+    if constexpr (V - 1 > 4) idx |= ((u >> 4) & ((1u << (V - 1 - 4)) - 1u)) << 5;
+    return idx;
+}
+
+// ---------------------------------------------------------------------------
+// Packed path-metric pairs
+// ---------------------------------------------------------------------------
+struct PM16 {
+    typedef short v2 __attribute__((ext_vector_type(2)));
+    typedef unsigned short v2u __attribute__((ext_vector_type(2)));
+    using T = v2;
+    static constexpr int kLimit = 32767;
+    static __device__ __forceinline__ T make(int lo, int hi) { return T{(short)lo, (short)hi}; }
+    static __device__ __forceinline__ T add(T a, T b) {
+        return __builtin_bit_cast(T, __builtin_bit_cast(v2u, a) + __builtin_bit_cast(v2u, b));
+    }
+    static __device__ __forceinline__ T sub(T a, T b) {
+        return __builtin_bit_cast(T, __builtin_bit_cast(v2u, a) - __builtin_bit_cast(v2u, b));
+    }
+    static __device__ __forceinline__ T vmin(T a, T b) { return __builtin_elementwise_min(a, b); }
+    static __device__ __forceinline__ T bcast_lo(T a) { return a.xx; }
+    static __device__ __forceinline__ T bcast_hi(T a) { return a.yy; }
+    // sign of (b - a) of each half at bits 0 and 16: 1 = b strictly smaller
+    static __device__ __forceinline__ uint32_t dec(T a, T b) {
+        v2u d = __builtin_bit_cast(v2u, sub(b, a));
+        d = d >> (v2u){15, 15};
+        return __builtin_bit_cast(uint32_t, d);
+    }
+    static __device__ __forceinline__ int lo(T a) { return a.x; }
+    static __device__ __forceinline__ int hi(T a) { return a.y; }
+};
+
+struct PM32 {
+    struct T { int x, y; };
+    static constexpr int kLimit = 0x7fffffff;
+    static __device__ __forceinline__ T make(int lo, int hi) { return T{lo, hi}; }
+    static __device__ __forceinline__ T add(T a, T b) { return T{a.x + b.x, a.y + b.y}; }
+    static __device__ __forceinline__ T sub(T a, T b) { return T{a.x - b.x, a.y - b.y}; }
+    static __device__ __forceinline__ T vmin(T a, T b) { return T{a.x < b.x ? a.x : b.x, a.y < b.y ? a.y : b.y}; }
+    static __device__ __forceinline__ T bcast_lo(T a) { return T{a.x, a.x}; }
+    static __device__ __forceinline__ T bcast_hi(T a) { return T{a.y, a.y}; }
+    static __device__ __forceinline__ uint32_t dec(T a, T b) {
+        return ((uint32_t)(b.x - a.x) >> 31) | (((uint32_t)(b.y - a.y) >> 31) << 16);
+    }
+    static __device__ __forceinline__ int lo(T a) { return a.x; }
+    static __device__ __forceinline__ int hi(T a) { return a.y; }
+};
+
+// acc | (x << SH) as one v_lshl_or_b32.  Written out so that the compiler
+// keeps one instruction per inserted decision pair instead of rebuilding the
+// OR chain as a shift-and-or tree.
+template <int SH>
+__device__ __forceinline__ uint32_t shl_or(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "n"(SH), "v"(acc));
+    return r;
+}
+
+enum { kSoftI8 = 0, kHardU8 = 1 };
+
+template <int KIND>
+__device__ __forceinline__ int rx_value(const uint8_t *p) {
+    if constexpr (KIND == kHardU8) return 1 - 2 * (int)(*p & 1u);
+    else return (int)(int8_t)*p;
+}
+
+// The 2^R distinct branch metrics of one stage (Sec. III-B: every branch
+// carries one of the 2^R code words): metric(c) = sum over r with c^(r) = 1
+// of q_r.  The Sec. II distance sum_r [c^(r) != (q_r < 0)] |q_r| equals this
+// plus sum_r max(-q_r, 0), which is the same for every c.
+template <int R>
+__device__ __forceinline__ void code_word_metrics(const int (&q)[R], int (&bm)[1 << R]) {
+#pragma unroll
+    for (int c = 0; c < (1 << R); ++c) {
+        int s = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if ((c >> (R - 1 - r)) & 1) s += q[r];
+        bm[c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One trellis stage at compile-time phase PH.  Writes the stage's decision
+// bits into dw[] at slot offset SLOT0 (in units of packed registers).
+// ---------------------------------------------------------------------------
+template <class C, class P, int PH, int SLOT0, int NDW>
+__device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int (&q)[C::R],
+                                          uint32_t (&dw)[NDW]) {
+    using T = typename P::T;
+    constexpr int V = C::V, NR = C::NR, NC = C::NC;
+    constexpr int G0 = C::gcol(0), GK = C::gcol(C::K - 1);
+
+    int bm[NC];
+    code_word_metrics<C::R>(q, bm);
+
+    if constexpr (PH < V - 1) {
+        // pairs (X, Y = X | 2^PH); halves differ in state bit V-1-PH
+        constexpr int GP = C::gcol(V - 1 - PH);
+        T pair[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pair[c] = P::make(bm[c], bm[c ^ GP]);
+        static_for<0, NR / 2>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int X = ((k >> PH) << (PH + 1)) | (k & ((1 << PH) - 1));
+            constexpr int Y = X | (1 << PH);
+            constexpr int alpha = C::out0(rotr_v<V>(X, PH));  // c(S_2j, 0) of the lower half
+            const T a0 = P::add(pm[X], pair[alpha]);
+            const T b0 = P::add(pm[Y], pair[alpha ^ G0]);
+            const T a1 = P::add(pm[X], pair[alpha ^ GK]);
+            const T b1 = P::add(pm[Y], pair[alpha ^ G0 ^ GK]);
+            pm[X] = P::vmin(a0, b0);
+            pm[Y] = P::vmin(a1, b1);
+            constexpr int sx = SLOT0 + X, sy = SLOT0 + Y;
+            dw[sx >> 4] = shl_or<(sx & 15)>(P::dec(a0, b0), dw[sx >> 4]);
+            dw[sy >> 4] = shl_or<(sy & 15)>(P::dec(a1, b1), dw[sy >> 4]);
+            return true;
+        });
+    } else {
+        // each register holds (S_2j, S_2j+1): broadcast operands
+        T pair[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pair[c] = P::make(bm[c], bm[c ^ GK]);
+        static_for<0, NR>([&](auto xc) {
+            constexpr int X = decltype(xc)::value;
+            constexpr int alpha = C::out0(2 * X);
+            const T a = P::add(P::bcast_lo(pm[X]), pair[alpha]);
+            const T b = P::add(P::bcast_hi(pm[X]), pair[alpha ^ G0]);
+            pm[X] = P::vmin(a, b);
+            constexpr int sx = SLOT0 + X;
+            dw[sx >> 4] = shl_or<(sx & 15)>(P::dec(a, b), dw[sx >> 4]);
+            return true;
+        });
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time layout constants of one code
+// ---------------------------------------------------------------------------
+template <class C, class P>
+struct Layout {
+    static constexpr int V = C::V, NR = C::NR;
+    static constexpr int NDW = NR >= 16 ? NR / 16 : 1;   // survivor dwords per stored row
+    static constexpr int S = NR >= 16 ? 1 : 16 / NR;      // stages per stored row
+    static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+    static constexpr int U = V / gcd(V, S) * S;           // unrolled stages per loop trip
+    // Largest metric spread: the known-state start (8192) plus K-1 stages of
+    // the widest branch-metric difference (128 per symbol).  Between two
+    // renormalizations every metric moves by at most 128*R per stage.
+    static constexpr int kSpread = 8192 + V * 128 * C::R;
+    static constexpr long long kMaxStages = ((long long)P::kLimit - kSpread) / (128LL * C::R);
+    static constexpr int kRenormTrips =
+        kMaxStages / U > (1 << 30) ? (1 << 30) : (int)(kMaxStages / U);
+    static_assert(kRenormTrips >= 1, "metric range too small for this code");
+};
+
+template <int V>
+__device__ __forceinline__ int rotr_rt(int u, int s) {
+    return ((u >> s) | (u << (V - s))) & ((1 << V) - 1);
+}
+
+template <int V>
+__device__ __forceinline__ int ubit_pos_rt(int t) {
+    return t == V - 1 ? 4 : (t < 4 ? t : t + 1);
+}
+
+// ---------------------------------------------------------------------------
+// The decoder kernel: forward ACS with survivor stores, final metrics, then
+// traceback with packed output, for every PB of the launch.
+// ---------------------------------------------------------------------------
+template <class C, class P, int KIND>
+__global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
+    using T = typename P::T;
+    using LY = Layout<C, P>;
+    constexpr int V = C::V, N = C::N, NR = C::NR, R = C::R;
+    constexpr int NDW = LY::NDW, S = LY::S, U = LY::U;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    // wave index made provably uniform so that all geometry stays scalar
+    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave_local >= a.n_waves) return;
+    const int64_t wave = a.wave_begin + wave_local;
+    const int64_t D = a.D, L = a.L;
+
+    // ---- block geometry (Sec. III-A with M = L, clipped to the stream) ----
+    int64_t b, f0w, f1w, d0w, d1w;   // wave-uniform PB geometry (interior: lane 0's)
+    bool active;
+    int64_t lane_stage_off;           // this lane's stage offset from f0w
+    if (wave < a.n_int_waves) {
+        const int64_t bw = a.b_lo + wave * kWave;
+        b = bw + lane;
+        active = b < a.b_hi;
+        lane_stage_off = (active ? (int64_t)lane : (a.b_hi - 1 - bw)) * D;
+        if (!active) b = a.b_hi - 1;
+        d0w = bw * D;
+        f0w = d0w - L;
+        f1w = d0w + D + L;
+        d1w = d0w + D;
+    } else {
+        const int64_t e = wave - a.n_int_waves;
+        b = e < a.n_head ? a.pb_first + e : a.b_hi + (e - a.n_head);
+        active = lane == 0;
+        lane_stage_off = 0;
+        d0w = b * D;
+        f0w = d0w - L < 0 ? 0 : d0w - L;
+        f1w = d0w + D + L > a.T ? a.T : d0w + D + L;
+        d1w = d0w + D > a.n ? a.n : d0w + D;
+    }
+    // stage counts fit in 32 bits (at most D + 2L), which keeps the loop
+    // control on the scalar unit
+    const int len = (int)(f1w - f0w);         // forward stages
+    const int i_store0 = (int)(d0w - f0w);    // first stored / traced stage
+    const int i_dec_end = (int)(d1w - f0w);   // end of the decoded range
+    const uint8_t *in = a.syms + (f0w + lane_stage_off) * R;
+    uint32_t *spw = a.sp + wave_local * a.sp_wave_dwords;
+    const int k0 = i_store0 / S;              // first stored row
+
+    // ---- initial metrics ----
+    T pm[NR];
+    {
+        const int big = f0w == 0 ? 8192 : 0;  // known start state 0 at stage 0
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? 0 : big, big);
+    }
+
+    // ---- forward procedure ----
+    int qc[U][R], qn[U][R];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        const int st = k < len ? k : len - 1;
+#pragma unroll
+        for (int r = 0; r < R; ++r) qc[k][r] = rx_value<KIND>(in + st * R + r);
+    }
+    uint32_t dw[NDW];
+#pragma unroll
+    for (int w = 0; w < NDW; ++w) dw[w] = 0;
+    int trips_since_renorm = 0;
+    for (int i0 = 0;; i0 += U) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int st0 = i0 + U + k;
+            const int st = st0 < len ? st0 : len - 1;
+#pragma unroll
+            for (int r = 0; r < R; ++r) qn[k][r] = rx_value<KIND>(in + st * R + r);
+        }
+        if (++trips_since_renorm == LY::kRenormTrips) {
+            trips_since_renorm = 0;
+            const T ref = P::bcast_lo(pm[0]);
+#pragma unroll
+            for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
+        }
+        const bool more = static_for<0, U>([&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            if (i0 + k >= len) return false;
+            acs_stage<C, P, k % V, (k % S) * NR, NDW>(pm, qc[k], dw);
+            if ((k % S) == S - 1 || i0 + k + 1 == len) {
+                const int row = (i0 + k) / S;
+                if (row >= k0) {
+                    uint32_t *dst = spw + ((int64_t)(row - k0) * kWave + lane) * NDW;
+                    if constexpr (NDW == 1) {
+                        dst[0] = dw[0];
+                    } else if constexpr (NDW == 2) {
+                        *reinterpret_cast<uint2 *>(dst) = make_uint2(dw[0], dw[1]);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < NDW; w += 4)
+                            *reinterpret_cast<uint4 *>(dst + w) =
+                                make_uint4(dw[w], dw[w + 1], dw[w + 2], dw[w + 3]);
+                    }
+                }
+#pragma unroll
+                for (int w = 0; w < NDW; ++w) dw[w] = 0;
+            }
+            return true;
+        });
+        if (!more || i0 + U >= len) break;
+#pragma unroll
+        for (int k = 0; k < U; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) qc[k][r] = qn[k][r];
+    }
+
+    // ---- final metrics and traceback start (Sec. III-A; Sec. II at an
+    //      unterminated stream end) ----
+    const int ph_end = (int)(len % V);
+    const bool argmin_start = f1w == a.T && !a.terminated;
+    uint32_t idx = 0;  // rotated index of state 0 is 0
+    if (argmin_start || a.final_pm) {
+        int m = 0x7fffffff;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            m = min(m, P::lo(pm[r]));
+            m = min(m, P::hi(pm[r]));
+        }
+        if (argmin_start) {
+            int best = N;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int s_lo = rotr_rt<V>(r, ph_end), s_hi = rotr_rt<V>(r + NR, ph_end);
+                if (P::lo(pm[r]) == m && s_lo < best) best = s_lo;
+                if (P::hi(pm[r]) == m && s_hi < best) best = s_hi;
+            }
+            idx = u_to_idx<V>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
+        }
+        if (a.final_pm && active) {
+            int32_t *fp = a.final_pm + (b - a.pb_first) * N;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                fp[rotr_rt<V>(r, ph_end)] = P::lo(pm[r]) - m;
+                fp[rotr_rt<V>(r + NR, ph_end)] = P::hi(pm[r]) - m;
+            }
+        }
+    }
+
+    // ---- traceback (Sec. III-A, Alg. 1) ----
+    const int64_t out_bit0 = (b - a.pb_first) * D;
+    const int n_dec = i_dec_end - i_store0;
+    uint32_t word = 0;
+    int ph = (int)((len - 1) % V);
+    for (int i = len - 1; i >= i_store0; --i) {
+        const int qpos = ubit_pos_rt<V>(ph);
+        const uint32_t x = (idx >> qpos) & 1u;
+        if (i < i_dec_end) {
+            word = (word << 1) | x;
+            const int rel = i - i_store0;
+            if ((rel & 31) == 0) {
+                const int m = n_dec - rel < 32 ? n_dec - rel : 32;
+                const int64_t bitpos = out_bit0 + rel;
+                if (active) {
+                    if (a.direct_out) {
+                        const int64_t byte = bitpos >> 3;
+                        if (m == 32 && byte + 4 <= a.out_bytes) {
+                            *reinterpret_cast<uint32_t *>(a.out + byte) = word;
+                        } else {
+                            for (int bb = 0; bb < ((m + 7) >> 3); ++bb)
+                                if (byte + bb < a.out_bytes) a.out[byte + bb] = (uint8_t)(word >> (8 * bb));
+                        }
+                    } else {
+                        const uint32_t sh = (uint32_t)(bitpos & 31);
+                        uint32_t *wp = a.out_words + (bitpos >> 5);
+                        atomicOr(wp, word << sh);
+                        if (sh && (word >> (32 - sh))) atomicOr(wp + 1, word >> (32 - sh));
+                    }
+                }
+                word = 0;
+            }
+        }
+        uint32_t dec;
+        if constexpr (NR >= 16) {
+            const uint32_t w = spw[((int64_t)(i - i_store0) * kWave + lane) * NDW + (idx >> 5)];
+            dec = (w >> (idx & 31u)) & 1u;
+        } else {
+            const uint32_t w = spw[((int64_t)(i / S - k0) * kWave + lane)];
+            dec = (w >> (idx + (uint32_t)(i % S) * NR)) & 1u;
+        }
+        idx = (idx & ~(1u << qpos)) | (dec << qpos);
+        ph = ph == 0 ? V - 1 : ph - 1;
+    }
+}
+
+}  // namespace pbvd

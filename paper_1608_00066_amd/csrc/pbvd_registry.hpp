@@ -1,0 +1,67 @@
+// Codes that have decoder kernels compiled in, and the launch interface each
+// per-code translation unit implements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pbvd_kernel.hpp"
+
+// X(index, K, R, g0, g1, g2, g3): generators in octal, gen[r] bit k = g_k.
+// The first four are the codes of the benchmark workloads; the others are
+// common maximum-free-distance codes for every K in 3..9 and R in 2..4, plus
+// two codes whose first and last taps differ between generators.
+#define PBVD_CODE_LIST(X)                   \
+    X(0, 3, 2, 07, 05, 0, 0)                \
+    X(1, 7, 2, 0171, 0133, 0, 0)            \
+    X(2, 7, 3, 0133, 0171, 0165, 0)         \
+    X(3, 9, 3, 0557, 0663, 0711, 0)         \
+    X(4, 3, 2, 05, 07, 0, 0)                \
+    X(5, 4, 2, 015, 017, 0, 0)              \
+    X(6, 5, 2, 023, 035, 0, 0)              \
+    X(7, 6, 2, 053, 075, 0, 0)              \
+    X(8, 7, 2, 0133, 0171, 0, 0)            \
+    X(9, 8, 2, 0247, 0371, 0, 0)            \
+    X(10, 9, 2, 0561, 0753, 0, 0)           \
+    X(11, 3, 3, 05, 07, 07, 0)              \
+    X(12, 4, 3, 013, 015, 017, 0)           \
+    X(13, 5, 3, 025, 033, 037, 0)           \
+    X(14, 6, 3, 047, 053, 075, 0)           \
+    X(15, 5, 4, 025, 027, 033, 037)         \
+    X(16, 7, 4, 0117, 0127, 0155, 0171)     \
+    X(17, 5, 2, 031, 027, 0, 0)             \
+    X(18, 6, 2, 046, 073, 0, 0)
+
+#define PBVD_COUNT_ONE(i, K, R, g0, g1, g2, g3) +1
+constexpr int kNumCodes = 0 PBVD_CODE_LIST(PBVD_COUNT_ONE);
+#undef PBVD_COUNT_ONE
+
+struct RegisteredCode {
+    int K, R;
+    uint32_t gen[4];
+};
+
+// host-visible table, defined in pbvd_capi.hip
+extern const RegisteredCode kRegisteredCodes[kNumCodes];
+
+namespace pbvd {
+
+struct LaunchRequest {
+    KernelArgs args;
+    int pm_bits;        // 16 or 32
+    int input_kind;     // kSoftI8 or kHardU8
+    unsigned grid;      // workgroups of kBlockThreads
+    hipStream_t stream;
+};
+
+constexpr int kBlockThreads = 256;
+
+// Implemented by the translation unit compiled for code index IDX.
+template <int IDX>
+hipError_t launch_code(const LaunchRequest &req);
+
+// Survivor layout of a code: dwords per stored row and stages per row.
+__host__ __device__ constexpr int survivor_row_dwords(int K) { return (1 << (K - 2)) >= 16 ? (1 << (K - 2)) / 16 : 1; }
+__host__ __device__ constexpr int survivor_row_stages(int K) { return (1 << (K - 2)) >= 16 ? 1 : 16 / (1 << (K - 2)); }
+
+}  // namespace pbvd

@@ -1,0 +1,108 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports
+every entry point include/pbvd.h declares, validates arguments, and its
+block geometry matches the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pbvd():
+    from paper_1608_00066_amd import pbvd as mod
+    if not os.path.exists(mod.LIB_PATH):
+        from paper_1608_00066_amd import build
+        build.build()
+    mod.lib()
+    return mod
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "pbvd.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pbvd_[a-z_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(pbvd):
+    names = header_functions()
+    assert len(names) >= 10
+    h = ctypes.CDLL(pbvd.LIB_PATH)
+    for name in names:
+        assert hasattr(h, name), name
+    assert set(names) == set(pbvd.SIGNATURES)
+
+
+def test_strerror(pbvd):
+    assert pbvd.pbvd_strerror(0) == "success"
+    assert pbvd.pbvd_strerror(-1) == "invalid argument"
+    assert pbvd.pbvd_strerror(-4) == "HIP runtime error"
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(K=2), -1), (dict(K=10), -1), (dict(R=1), -1), (dict(R=5), -1),
+    (dict(gens=(0o171, 0o1133)), -1), (dict(gens=(0o71, 0o33)), -1), (dict(gens=(0o171, 0)), -1),
+    (dict(D=0), -1), (dict(L=-1), -1), (dict(D=1 << 29, L=1 << 28), -1),
+    (dict(input_kind=2), -1), (dict(pm_bits=8), -1), (dict(terminated=2), -1),
+    (dict(gens=(0o171, 0o135)), -2),
+    (dict(K=9, gens=(0o557, 0o663, 0o711), pm_bits=32), -2),
+])
+def test_create_validation(pbvd, kw, status):
+    args = dict(K=7, gens=(0o171, 0o133), D=512, L=42, terminated=True, input_kind=0, pm_bits=16)
+    if "R" in kw:
+        args["gens"] = (0o171,) * kw.pop("R")
+    args.update(kw)
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.pbvd_create(**args)
+    assert ei.value.status == status
+    assert pbvd.pbvd_last_error()
+
+
+def test_decode_argument_validation(pbvd):
+    h = pbvd.pbvd_create(7, (0o171, 0o133), 512, 42)
+    try:
+        L = pbvd.lib()
+        fake = ctypes.c_void_p(0x1000)
+        plan = ctypes.c_void_p(h)
+        assert L.pbvd_decode(None, fake, 10, fake, None) == -1
+        assert L.pbvd_decode(plan, None, 10, fake, None) == -1
+        assert L.pbvd_decode(plan, fake, 0, fake, None) == -1
+        assert L.pbvd_decode(plan, fake, 10, None, None) == -1
+        assert L.pbvd_decode_ex(plan, fake, 1000, 0, 3, fake, None, None) == -1  # 2 PBs only
+        assert L.pbvd_decode_ex(plan, fake, 1000, -1, 1, fake, None, None) == -1
+        assert L.pbvd_decode_ex(plan, fake, 1000, 2, 0, None, None, None) == 0   # empty range
+        assert L.pbvd_debug_branch_metrics(plan, None, 5, fake, None) == -1
+        assert L.pbvd_debug_survivors(plan, fake, 1000, 0, 1, fake, None, None) == -1
+        assert L.pbvd_num_blocks(plan, 1025) == 3
+        assert L.pbvd_num_blocks(plan, 0) == 0
+    finally:
+        pbvd.pbvd_destroy(h)
+
+
+@pytest.mark.parametrize("K,gens,D,L,n,term", [
+    (7, (0o171, 0o133), 512, 42, 1 << 20, True),
+    (3, (0o7, 0o5), 256, 32, 4096, True),
+    (9, (0o557, 0o663, 0o711), 2048, 54, 100000, True),
+    (5, (0o23, 0o35), 7, 40, 333, False),
+    (5, (0o23, 0o35), 1, 0, 17, True),
+    (4, (0o15, 0o17), 1000, 5, 10, True),
+])
+def test_block_geometry_matches_oracle(pbvd, K, gens, D, L, n, term):
+    h = pbvd.pbvd_create(K, gens, D, L, term)
+    try:
+        nb = pbvd.pbvd_num_blocks(h, n)
+        assert nb == oracle.num_blocks(n, D)
+        geo = pbvd.pbvd_block_geometry(h, n, 0, nb)
+        T = n + (K - 1 if term else 0)
+        want = np.array([oracle.pb_geometry(n, T, D, L, b) for b in range(nb)], dtype=np.int64)
+        assert np.array_equal(geo, want)
+        sub = pbvd.pbvd_block_geometry(h, n, nb // 2, nb - nb // 2)
+        assert np.array_equal(sub, want[nb // 2:])
+    finally:
+        pbvd.pbvd_destroy(h)

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP decoder (through the C ABI) against the CPU oracle.
+
+Bit-exact on decoded bits, normalized final path metrics and survivor
+decisions (the oracle's int64 arithmetic is exact, and so is the kernel's
+int16/int32 arithmetic within its proven range), plus branch metrics up to
+the per-stage constant the kernel drops.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00066_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+NTHREADS = min(16, os.cpu_count() or 4)
+
+C1 = dict(K=3, gens=(0o7, 0o5), D=256, L=32, kind=datagen.HARD_U8, pm_bits=32)
+C2 = dict(K=7, gens=(0o171, 0o133), D=512, L=42, kind=datagen.SOFT_I8, pm_bits=16)
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def pbvd():
+    from paper_1608_00066_amd import pbvd as mod
+    mod.lib()
+    return mod
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def gpu_bits(torch, out, nbits):
+    torch.cuda.synchronize()
+    return np.unpackbits(out.cpu().numpy(), bitorder="little")[:nbits]
+
+
+def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=True):
+    """Decode PBs [pb_first, pb_first+pb_count) on GPU and oracle; compare
+    bits, normalized final metrics and (optionally) survivor decisions."""
+    K, gens, n, kind = st["K"], st["gens"], st["n"], st["kind"]
+    term = st["terminated"]
+    with pbvd.Plan(K, gens, D, L, term, kind, pm_bits) as plan:
+        dsyms = to_dev(torch, st["syms"])
+        nbits = plan.out_bits(n, pb_first, pb_count)
+        out, fpm = plan.decode_ex(dsyms, n, pb_first, pb_count, want_pm=True)
+        got_bits = gpu_bits(torch, out, nbits)
+        got_pm = fpm.cpu().numpy()[:pb_count]
+        ref = oracle.decode(K, gens, D, L, st["syms"], n, terminated=term, input_kind=kind,
+                            pb_first=pb_first, pb_count=pb_count, want_pm=True,
+                            want_dec=survivors, nthreads=NTHREADS)
+        assert got_bits.size == ref["bits"].size
+        mism = np.flatnonzero(got_bits != ref["bits"])
+        assert mism.size == 0, "bit mismatches at %s" % mism[:10]
+        assert np.array_equal(got_pm, ref["final_pm"]), "final metric mismatch"
+        if survivors:
+            out2, dec = plan.debug_survivors(dsyms, n, pb_first, pb_count)
+            assert np.array_equal(gpu_bits(torch, out2, nbits), ref["bits"])
+            got_dec = dec.cpu().numpy()[:pb_count]
+            bad = np.argwhere(got_dec != ref["dec"])
+            assert bad.size == 0, "survivor mismatches (pb,row,state) %s" % bad[:5]
+    return ref
+
+
+def test_c1_hard_k3_int32(torch, pbvd):
+    log("C1 K=3 hard int32 D=256 L=32 n=4096 4dB")
+    st = datagen.make_stream(3, (0o7, 0o5), 4096, 4.0, datagen.config_seed(0, 4.0),
+                             kind=datagen.HARD_U8)
+    ref = check_range(torch, pbvd, st, 256, 32, 32, 0, 16)
+    # same through pbvd_decode and with int16 metrics
+    with pbvd.Plan(3, (0o7, 0o5), 256, 32, True, datagen.HARD_U8, 16) as plan:
+        out = plan.decode(to_dev(torch, st["syms"]), 4096)
+        assert np.array_equal(gpu_bits(torch, out, 4096), ref["bits"])
+
+
+@pytest.mark.parametrize("ebn0", [2.0, 3.0, 4.0, 5.0])
+def test_c2_k7_soft_full_stream(torch, pbvd, ebn0):
+    n = 1 << 20
+    log("C2 K=7 soft D=512 L=42 n=2^20 %.0fdB" % ebn0)
+    st = datagen.make_stream(7, (0o171, 0o133), n, ebn0, datagen.config_seed(1, ebn0))
+    with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
+        out = plan.decode(to_dev(torch, st["syms"]), n)
+        got = gpu_bits(torch, out, n)
+    ref = oracle.decode(7, (0o171, 0o133), 512, 42, st["syms"], n, nthreads=NTHREADS)
+    assert np.array_equal(got, ref["bits"])
+    # metrics and survivors on the first, middle and last blocks
+    for a, c in [(0, 3), (1000, 64), (2045, 3)]:
+        check_range(torch, pbvd, st, 512, 42, 16, a, c)
+    if ebn0 >= 4.0:
+        assert np.mean(got != st["info"]) < 1e-3
+
+
+@pytest.fixture(scope="module")
+def c3_streams():
+    n = 1 << 27
+    log("C3 generating 2^27-bit streams")
+    s7 = datagen.make_stream(7, (0o171, 0o133), n, 3.0, datagen.config_seed(2, 3.0, 0))
+    s9 = datagen.make_stream(9, (0o557, 0o663, 0o711), n, 3.0, datagen.config_seed(2, 3.0, 1))
+    return {7: s7, 9: s9}
+
+
+@pytest.mark.parametrize("K", [7, 9])
+@pytest.mark.parametrize("D", [256, 512, 1024, 2048])
+def test_c3_full_size_sampled(torch, pbvd, c3_streams, K, D):
+    """2^27-bit streams decoded whole on the GPU (the benchmark's launch);
+    sampled blocks compared with the oracle; the BER of the whole stream
+    checked against the oracle's on the samples' statistics."""
+    st = c3_streams[K]
+    n, gens, L = st["n"], st["gens"], 6 * K
+    log("C3 K=%d D=%d L=%d full stream" % (K, D, L))
+    with pbvd.Plan(K, gens, D, L) as plan:
+        dsyms = to_dev(torch, st["syms"])
+        out = plan.decode(dsyms, n)
+        got = gpu_bits(torch, out, n)
+        nb = plan.num_blocks(n)
+    rng = np.random.default_rng(D + K)
+    picks = [0, 1, nb - 2, nb - 1] + sorted(rng.choice(np.arange(2, nb - 2), 12, replace=False).tolist())
+    for b in picks:
+        ref = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=b, pb_count=1)
+        assert np.array_equal(got[b * D: b * D + ref["bits"].size], ref["bits"]), "PB %d" % b
+    ber = float(np.mean(got != st["info"]))
+    assert ber < datagen.uncoded_ber(3.0)
+    # metrics/survivors of a few blocks in the same configuration
+    check_range(torch, pbvd, st, D, L, 16, nb // 2, 2, survivors=(K == 7))
+
+
+def fuzz_cases():
+    rng = np.random.default_rng(1234)
+    codes = [(3, (0o7, 0o5)), (7, (0o171, 0o133)), (7, (0o133, 0o171, 0o165)),
+             (9, (0o557, 0o663, 0o711)), (3, (0o5, 0o7)), (4, (0o15, 0o17)), (5, (0o23, 0o35)),
+             (6, (0o53, 0o75)), (7, (0o133, 0o171)), (8, (0o247, 0o371)), (9, (0o561, 0o753)),
+             (3, (0o5, 0o7, 0o7)), (4, (0o13, 0o15, 0o17)), (5, (0o25, 0o33, 0o37)),
+             (6, (0o47, 0o53, 0o75)), (5, (0o25, 0o27, 0o33, 0o37)),
+             (7, (0o117, 0o127, 0o155, 0o171)), (5, (0o31, 0o27)), (6, (0o46, 0o73))]
+    cases = []
+    for i in range(40):
+        K, gens = codes[i % len(codes)]
+        n = int(rng.integers(1, 5000))
+        D = int(rng.choice([1, 3, 8, 32, 64, 100, 256, 999, 4096, 8192]))
+        L = int(rng.choice([0, 1, 5, K, 6 * K, 200, 6000]))
+        term = bool(rng.integers(0, 2))
+        kind = int(rng.integers(0, 2))
+        pm = 32 if (K <= 8 and rng.random() < 0.3) else 16
+        ebn0 = float(rng.choice([0.0, 2.0, 4.0]))
+        # keep the oracle's work (blocks x forward stages x states) small
+        while n > 1 and -(-n // D) * min(n + K, D + 2 * L) * (1 << (K - 1)) > 3e7:
+            n //= 2
+        cases.append((i, K, gens, n, D, L, term, kind, pm, ebn0))
+    # fixed edge cases: n=1, D >= n, L >= T, exact multiples, one PB per lane group
+    cases += [(100, 7, (0o171, 0o133), 1, 512, 42, True, 0, 16, 3.0),
+              (101, 7, (0o171, 0o133), 1, 512, 42, False, 0, 16, 3.0),
+              (102, 7, (0o171, 0o133), 64 * 64, 64, 42, True, 0, 16, 2.0),
+              (103, 7, (0o171, 0o133), 64 * 64 + 1, 64, 42, False, 0, 16, 2.0),
+              (104, 9, (0o557, 0o663, 0o711), 3000, 96, 54, True, 0, 16, 1.0),
+              (105, 5, (0o23, 0o35), 700, 7, 800, False, 1, 32, 1.0),
+              (106, 3, (0o7, 0o5), 129 * 8, 8, 3, True, 1, 32, 4.0)]
+    return cases
+
+
+@pytest.mark.parametrize("case", fuzz_cases(), ids=lambda c: "f%d" % c[0])
+def test_fuzz_parity(torch, pbvd, case):
+    i, K, gens, n, D, L, term, kind, pm, ebn0 = case
+    log("fuzz %d: K=%d R=%d n=%d D=%d L=%d term=%d kind=%d pm=%d" % (i, K, len(gens), n, D, L,
+                                                                      term, kind, pm))
+    st = datagen.make_stream(K, gens, n, ebn0, seed=5000 + i, kind=kind, terminated=term)
+    nb = oracle.num_blocks(n, D)
+    check_range(torch, pbvd, st, D, L, pm, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7)
+
+
+def test_split_invariance_and_misaligned_output(torch, pbvd):
+    n, D, L = 20000, 512, 42
+    st = datagen.make_stream(7, (0o171, 0o133), n, 2.0, seed=77)
+    dsyms = to_dev(torch, st["syms"])
+    with pbvd.Plan(7, (0o171, 0o133), D, L) as plan:
+        whole = gpu_bits(torch, plan.decode(dsyms, n), n)
+        nb = plan.num_blocks(n)
+        parts = []
+        for a, b in [(0, 5), (5, 6), (6, nb)]:
+            out, _ = plan.decode_ex(dsyms, n, a, b - a)
+            parts.append(gpu_bits(torch, out, plan.out_bits(n, a, b - a)))
+        assert np.array_equal(np.concatenate(parts), whole)
+        # output pointer that is not 4-byte aligned takes the staging path
+        buf = torch.zeros(n // 8 + 8, dtype=torch.uint8, device="cuda")
+        view = buf[1:1 + (n + 7) // 8]
+        plan.decode(dsyms, n, out=view)
+        assert np.array_equal(gpu_bits(torch, view, n), whole)
+        assert buf[0].item() == 0
+        # repeated runs are identical
+        again = gpu_bits(torch, plan.decode(dsyms, n), n)
+        assert np.array_equal(again, whole)
+
+
+@pytest.mark.parametrize("K,gens,kind", [(7, (0o171, 0o133), 0), (7, (0o133, 0o171, 0o165), 0),
+                                         (5, (0o25, 0o27, 0o33, 0o37), 0), (3, (0o7, 0o5), 1)])
+def test_branch_metrics_match_up_to_stage_constant(torch, pbvd, K, gens, kind):
+    R = len(gens)
+    rng = np.random.default_rng(9)
+    syms = rng.integers(0, 256, 5000 * R, dtype=np.uint8)
+    syms[:R] = 0x80  # -128
+    with pbvd.Plan(K, gens, 64, 6, True, kind) as plan:
+        bm = plan.debug_branch_metrics(to_dev(torch, syms), 5000)
+        torch.cuda.synchronize()
+        got = bm.cpu().numpy().astype(np.int64)
+    ref = oracle.branch_metrics(R, syms, kind)
+    assert np.array_equal(got - got[:, :1], ref - ref[:, :1])
+
+
+def test_injected_launch_failure_writes_nothing(torch, pbvd, monkeypatch):
+    n = 4096
+    st = datagen.make_stream(7, (0o171, 0o133), n, 3.0, seed=3)
+    dsyms = to_dev(torch, st["syms"])
+    with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
+        out = torch.full(((n + 7) // 8,), 0xA5, dtype=torch.uint8, device="cuda")
+        monkeypatch.setenv("PBVD_FAULT_INJECT", "launch")
+        with pytest.raises(pbvd.PbvdError) as ei:
+            plan.decode(dsyms, n, out=out)
+        assert ei.value.status == pbvd.PBVD_EHIP
+        torch.cuda.synchronize()
+        assert bool((out == 0xA5).all())
+        monkeypatch.delenv("PBVD_FAULT_INJECT")
+        plan.decode(dsyms, n, out=out)  # retry after the failure decodes normally
+        ref = oracle.decode(7, (0o171, 0o133), 512, 42, st["syms"], n)
+        assert np.array_equal(gpu_bits(torch, out, n), ref["bits"])
+
+
+def test_workspace_chunking(torch, pbvd, monkeypatch):
+    """A tiny workspace limit forces many launches; results do not change."""
+    n = 300000
+    st = datagen.make_stream(7, (0o171, 0o133), n, 2.5, seed=12)
+    dsyms = to_dev(torch, st["syms"])
+    with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
+        ref = gpu_bits(torch, plan.decode(dsyms, n), n)
+    monkeypatch.setenv("PBVD_WORKSPACE_MB", "1")
+    with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
+        got = gpu_bits(torch, plan.decode(dsyms, n), n)
+    assert np.array_equal(got, ref)
