@@ -42,20 +42,25 @@ def _run(cmd):
     return out
 
 
-def build(jobs: int | None = None, verbose: bool = False) -> str:
-    """Compile every unit and link ``libpbvd.so``; returns its path."""
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
+          build_dir: str = BUILD_DIR, lib: str = LIB, defines=()) -> str:
+    """Compile every unit and link ``libpbvd.so``; returns its path.
+    ``csrc``/``build_dir``/``lib``/``defines`` let a copy of the sources be
+    built elsewhere with other tuning macros."""
+    os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
+    flags = [f if f.startswith("-") else "-D" + f for f in defines]
+    flags += ["-I", csrc]
     units = []
     for i in range(num_codes()):
-        units.append((os.path.join(CSRC, "pbvd_code_inst.hip"),
-                      os.path.join(BUILD_DIR, "code_%02d.o" % i), ["-DPBVD_CODE_IDX=%d" % i]))
+        units.append((os.path.join(csrc, "pbvd_code_inst.hip"),
+                      os.path.join(build_dir, "code_%02d.o" % i), ["-DPBVD_CODE_IDX=%d" % i]))
     for name in ("pbvd_capi", "pbvd_aux"):
-        units.append((os.path.join(CSRC, name + ".hip"), os.path.join(BUILD_DIR, name + ".o"), []))
+        units.append((os.path.join(csrc, name + ".hip"), os.path.join(build_dir, name + ".o"), []))
 
     def compile_unit(u):
         src, obj, extra = u
-        _run([HIPCC, *COMMON, *extra, "-c", src, "-o", obj])
+        _run([HIPCC, *COMMON[:-2], *flags, *extra, "-c", src, "-o", obj])
         if verbose:
             print("built", os.path.basename(obj), flush=True)
         return obj
@@ -63,10 +68,10 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     # longest units first (K=9 kernels)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_unit, sorted(units, key=lambda u: u[1])))
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *sorted(objs)])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

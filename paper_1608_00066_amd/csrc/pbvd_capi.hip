@@ -59,7 +59,11 @@ CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int6
     g.pb_end = pb_first + pb_count;
     int64_t lo = ceil_div(L, D);
     if (lo < pb_first) lo = pb_first;
-    const int64_t lim = (g.T - D - L) < (n - D) ? (g.T - D - L) : (n - D);
+    // interior: bD + D + L <= T and bD + D <= n; on an unterminated stream a
+    // block ending exactly at T starts its traceback from the best state,
+    // so it is handled as an edge block
+    const int64_t tlim = g.T - D - L - (c.terminated ? 0 : 1);
+    const int64_t lim = tlim < (n - D) ? tlim : (n - D);
     int64_t hi = lim < 0 ? 0 : lim / D + 1;
     if (hi > g.pb_end) hi = g.pb_end;
     if (lo < hi) {

@@ -288,8 +288,16 @@ __device__ __forceinline__ int ubit_pos_rt(int t) {
 // The decoder kernel: forward ACS with survivor stores, final metrics, then
 // traceback with packed output, for every PB of the launch.
 // ---------------------------------------------------------------------------
+// Register target for the 256-state trellis: its 128 packed metrics leave
+// room for two waves per SIMD only if the compiler is asked for it.
+#ifndef PBVD_BIG_TRELLIS_WAVES_PER_EU
+#define PBVD_BIG_TRELLIS_WAVES_PER_EU 2
+#endif
+
 template <class C, class P, int KIND>
-__global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    decode_kernel(const KernelArgs a) {
     using T = typename P::T;
     using LY = Layout<C, P>;
     constexpr int V = C::V, N = C::N, NR = C::NR, R = C::R;
@@ -339,31 +347,72 @@ __global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
     // ---- initial metrics ----
     T pm[NR];
     {
-        const int big = f0w == 0 ? 8192 : 0;  // known start state 0 at stage 0
+        // known start state 0 when this lane's forward range starts at stage 0
+        // (an interior PB can, when L is a multiple of D)
+        const int big = f0w + lane_stage_off == 0 ? 8192 : 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? 0 : big, big);
     }
 
     // ---- forward procedure ----
-    int qc[U][R], qn[U][R];
+    // Received symbols of one loop trip (U stages, NB bytes) are fetched with
+    // one wide dword-aligned load per lane a trip ahead of their use, then
+    // shifted into place (each lane's block starts at its own byte offset).
+    // Only a window that would run past the end of the input falls back to
+    // byte loads.
+    constexpr int NB = U * R;
+    constexpr int NW = (NB + 3) / 4;   // dwords holding the trip's symbols
+    constexpr int ND = NW + 1;         // dwords fetched (unaligned start)
+    const uint8_t *const in_end = a.syms + a.T * R;
+    auto fetch = [&](uint32_t (&raw)[ND], uint32_t &sh, int i0) {
+        const uint8_t *p = in + (int64_t)i0 * R;
+        const uint32_t mis = (uint32_t)((uintptr_t)p & 3u);
+        const uint8_t *pa = p - mis;  // pointer arithmetic keeps the global address space
+        sh = mis * 8u;
+        if (pa + 4 * ND <= in_end) {
+            const uint32_t *q = reinterpret_cast<const uint32_t *>(pa);
 #pragma unroll
-    for (int k = 0; k < U; ++k) {
-        const int st = k < len ? k : len - 1;
+            for (int j = 0; j < ND; ++j) raw[j] = q[j];
+        } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) qc[k][r] = rx_value<KIND>(in + st * R + r);
+            for (int j = 0; j < ND; ++j) {
+                uint32_t v = 0;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    const uint8_t *c = pa + 4 * j + bb;
+                    if (c >= p && c < in_end) v |= (uint32_t)*c << (8 * bb);
+                }
+                raw[j] = v;
+            }
+        }
+    };
+    auto align_trip = [&](const uint32_t (&raw)[ND], uint32_t sh, uint32_t (&w)[NW]) {
+#pragma unroll
+        for (int j = 0; j < NW; ++j)
+            w[j] = (uint32_t)(((uint64_t)raw[j + 1] << 32 | raw[j]) >> sh);
+    };
+    auto symbols = [&](const uint32_t (&w)[NW], int k, int (&q)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int t = k * R + r;
+            const uint32_t byte = (w[t >> 2] >> (8 * (t & 3))) & 0xffu;
+            if constexpr (KIND == kHardU8) q[r] = 1 - 2 * (int)(byte & 1u);
+            else q[r] = (int)(int8_t)byte;
+        }
+    };
+    uint32_t raw_next[ND], sh_next, wsym[NW];
+    {
+        uint32_t raw0[ND], sh0;
+        fetch(raw0, sh0, 0);
+        align_trip(raw0, sh0, wsym);
     }
     uint32_t dw[NDW];
 #pragma unroll
     for (int w = 0; w < NDW; ++w) dw[w] = 0;
     int trips_since_renorm = 0;
     for (int i0 = 0;; i0 += U) {
-#pragma unroll
-        for (int k = 0; k < U; ++k) {
-            const int st0 = i0 + U + k;
-            const int st = st0 < len ? st0 : len - 1;
-#pragma unroll
-            for (int r = 0; r < R; ++r) qn[k][r] = rx_value<KIND>(in + st * R + r);
-        }
+        const bool last_trip = i0 + U >= len;
+        if (!last_trip) fetch(raw_next, sh_next, i0 + U);
         if (++trips_since_renorm == LY::kRenormTrips) {
             trips_since_renorm = 0;
             const T ref = P::bcast_lo(pm[0]);
@@ -373,7 +422,9 @@ __global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
         const bool more = static_for<0, U>([&](auto kc) {
             constexpr int k = decltype(kc)::value;
             if (i0 + k >= len) return false;
-            acs_stage<C, P, k % V, (k % S) * NR, NDW>(pm, qc[k], dw);
+            int q[R];
+            symbols(wsym, k, q);
+            acs_stage<C, P, k % V, (k % S) * NR, NDW>(pm, q, dw);
             if ((k % S) == S - 1 || i0 + k + 1 == len) {
                 const int row = (i0 + k) / S;
                 if (row >= k0) {
@@ -394,11 +445,8 @@ __global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
             }
             return true;
         });
-        if (!more || i0 + U >= len) break;
-#pragma unroll
-        for (int k = 0; k < U; ++k)
-#pragma unroll
-            for (int r = 0; r < R; ++r) qc[k][r] = qn[k][r];
+        if (!more || last_trip) break;
+        align_trip(raw_next, sh_next, wsym);
     }
 
     // ---- final metrics and traceback start (Sec. III-A; Sec. II at an
@@ -434,11 +482,43 @@ __global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
     }
 
     // ---- traceback (Sec. III-A, Alg. 1) ----
+    // The survivor rows of a PB do not depend on the state being traced, so
+    // blocks of TBR rows are loaded one block ahead of their use; only the
+    // bit selection inside a row follows the state.
+    constexpr int TBR = NDW >= 4 ? 4 : (NDW == 2 ? 8 : (16 / S));  // <= 16 stages, <= 32 dwords per block
+    const int row_lo = k0;
+    const int row_hi = (len - 1) / S;
     const int64_t out_bit0 = (b - a.pb_first) * D;
     const int n_dec = i_dec_end - i_store0;
     uint32_t word = 0;
-    int ph = (int)((len - 1) % V);
-    for (int i = len - 1; i >= i_store0; --i) {
+    int ph = (len - 1) % V;  // input phase of the stage being traced
+
+    auto load_block = [&](uint32_t (&dst)[TBR][NDW], int top) {
+#pragma unroll
+        for (int t = 0; t < TBR; ++t) {
+            const int row = top - t < row_lo ? row_lo : top - t;
+            const uint32_t *src = spw + ((int64_t)(row - row_lo) * kWave + lane) * NDW;
+            if constexpr (NDW == 1) {
+                dst[t][0] = src[0];
+            } else if constexpr (NDW == 2) {
+                const uint2 v = *reinterpret_cast<const uint2 *>(src);
+                dst[t][0] = v.x;
+                dst[t][1] = v.y;
+            } else {
+#pragma unroll
+                for (int w = 0; w < NDW; w += 4) {
+                    const uint4 v = *reinterpret_cast<const uint4 *>(src + w);
+                    dst[t][w] = v.x;
+                    dst[t][w + 1] = v.y;
+                    dst[t][w + 2] = v.z;
+                    dst[t][w + 3] = v.w;
+                }
+            }
+        }
+    };
+
+    // one traceback step at stage i with that stage's survivor row
+    auto step = [&](int i, const uint32_t (&row)[NDW], int sub) {
         const int qpos = ubit_pos_rt<V>(ph);
         const uint32_t x = (idx >> qpos) & 1u;
         if (i < i_dec_end) {
@@ -467,15 +547,57 @@ __global__ void __launch_bounds__(256) decode_kernel(const KernelArgs a) {
             }
         }
         uint32_t dec;
-        if constexpr (NR >= 16) {
-            const uint32_t w = spw[((int64_t)(i - i_store0) * kWave + lane) * NDW + (idx >> 5)];
-            dec = (w >> (idx & 31u)) & 1u;
+        if constexpr (NDW == 1) {
+            dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
+        } else if constexpr (NDW == 2) {
+            const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
+            dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
         } else {
-            const uint32_t w = spw[((int64_t)(i / S - k0) * kWave + lane)];
-            dec = (w >> (idx + (uint32_t)(i % S) * NR)) & 1u;
+            // select dword idx >> 5 with a binary tree, most significant
+            // index bit first (v[w + half] differs from v[w] in that bit)
+            uint32_t v[NDW];
+#pragma unroll
+            for (int w = 0; w < NDW; ++w) v[w] = row[w];
+            constexpr int kTopBit = 4 + (NDW >= 8 ? 3 : NDW >= 4 ? 2 : 1);
+#pragma unroll
+            for (int half = NDW / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
+                const bool up = (idx >> bit) & 1u;
+#pragma unroll
+                for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
+            }
+            dec = (v[0] >> (idx & 31u)) & 1u;
         }
         idx = (idx & ~(1u << qpos)) | (dec << qpos);
         ph = ph == 0 ? V - 1 : ph - 1;
+    };
+
+    // trace rows top..top-TBR+1; false once the first stored stage is passed
+    auto run_block = [&](const uint32_t (&blk)[TBR][NDW], int top) {
+        return static_for<0, TBR>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            const int row = top - t;
+            if (row < row_lo) return false;
+            return static_for<0, S>([&](auto sc) {
+                constexpr int sub = S - 1 - decltype(sc)::value;
+                const int i = row * S + sub;
+                if (i >= len) return true;
+                if (i < i_store0) return false;
+                step(i, blk[t], sub);
+                return true;
+            });
+        });
+    };
+
+    uint32_t ra[TBR][NDW], rb[TBR][NDW];
+    int top = row_hi;
+    load_block(ra, top);
+    for (;;) {
+        load_block(rb, top - TBR);
+        if (!run_block(ra, top)) break;
+        top -= TBR;
+        load_block(ra, top - TBR);
+        if (!run_block(rb, top)) break;
+        top -= TBR;
     }
 }
 

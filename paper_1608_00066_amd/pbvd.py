@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpbvd.so")
+# PBVD_LIBRARY may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("PBVD_LIBRARY") or os.path.join(_PKG, "libpbvd.so")
 
 PBVD_OK = 0
 PBVD_EINVAL = -1

@@ -168,7 +168,12 @@ def fuzz_cases():
               (103, 7, (0o171, 0o133), 64 * 64 + 1, 64, 42, False, 0, 16, 2.0),
               (104, 9, (0o557, 0o663, 0o711), 3000, 96, 54, True, 0, 16, 1.0),
               (105, 5, (0o23, 0o35), 700, 7, 800, False, 1, 32, 1.0),
-              (106, 3, (0o7, 0o5), 129 * 8, 8, 3, True, 1, 32, 4.0)]
+              (106, 3, (0o7, 0o5), 129 * 8, 8, 3, True, 1, 32, 4.0),
+              # interior blocks whose forward range starts at stage 0 (L a
+              # multiple of D): only that lane starts from the known state
+              (107, 7, (0o171, 0o133), 64 * 70, 64, 64, True, 0, 16, 1.0),
+              (108, 7, (0o171, 0o133), 128 * 100, 128, 0, True, 0, 16, 1.0),
+              (109, 9, (0o557, 0o663, 0o711), 3000, 27, 54, False, 0, 16, 0.0)]
     return cases
 
 
