@@ -117,6 +117,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary K=9 and 2^20-bit measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB five times (to scale the "
+                         "FETCH_SIZE/WRITE_SIZE counters of rocprofv3) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the decoder has no multi-GPU path in this "
@@ -130,6 +133,15 @@ def main():
     from paper_1608_00066_amd import datagen, pbvd
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": nbytes}), flush=True)
+        return
     pbvd.lib()
     K, gens, D, L, ebn0 = 7, (0o171, 0o133), 512, 42, 3.0
     n = 1 << args.log2_bits

@@ -288,10 +288,12 @@ __device__ __forceinline__ int ubit_pos_rt(int t) {
 // The decoder kernel: forward ACS with survivor stores, final metrics, then
 // traceback with packed output, for every PB of the launch.
 // ---------------------------------------------------------------------------
-// Register target for the 256-state trellis: its 128 packed metrics leave
-// room for two waves per SIMD only if the compiler is asked for it.
+// Register target for the 256-state trellis (waves per SIMD the compiler
+// must leave room for).  Two waves force scratch spills inside the stage
+// loop, which measured 2x slower than one wave with accumulator-register
+// spills.
 #ifndef PBVD_BIG_TRELLIS_WAVES_PER_EU
-#define PBVD_BIG_TRELLIS_WAVES_PER_EU 2
+#define PBVD_BIG_TRELLIS_WAVES_PER_EU 1
 #endif
 
 template <class C, class P, int KIND>
