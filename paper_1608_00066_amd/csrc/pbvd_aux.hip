@@ -55,7 +55,6 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
                 lane = 0;
             }
             const int i = (int)(d0 + row - f0);       // stage index inside the PB
-            const int i_store0 = (int)(d0 - f0);
             const int u = rotl_dyn(state, i + 1, V);  // register map after stage i
             const int r = u & (NR - 1), half = u >> (V - 1);
             const uint32_t *base = v.sp + wave * v.sp_wave_dwords;
@@ -63,12 +62,11 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
             int pos;
             if (NR >= 16) {
                 const int ndw = NR / 16;
-                w = base[((int64_t)(i - i_store0) * kWave + lane) * ndw + (r >> 4)];
-                pos = (r & 15) + 16 * half;
+                w = base[((int64_t)i * kWave + lane) * ndw + (r >> 4)];
+                pos = v.byte_perm ? 16 * (r & 1) + 8 * half + ((r & 15) >> 1) : (r & 15) + 16 * half;
             } else {
                 const int S = 16 / NR;
-                const int k0 = i_store0 / S;
-                w = base[(int64_t)(i / S - k0) * kWave + lane];
+                w = base[(int64_t)(i / S) * kWave + lane];
                 pos = (i % S) * NR + r + 16 * half;
             }
             bit = (uint8_t)((w >> pos) & 1u);

@@ -265,6 +265,15 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
         return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
     if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
     if (c.pm_bits == 32 && c.K > 8) return fail(PBVD_ENOTSUP, "32-bit path metrics need K <= 8");
+    {
+        // survivor rows of one wave slot are addressed with 32-bit offsets
+        const int64_t row_bytes = 64LL * pbvd::survivor_row_dwords(c.K) * 4;
+        const int64_t slot =
+            (((int64_t)c.D + 2 * (int64_t)c.L) / pbvd::survivor_row_stages(c.K) + 2) * row_bytes;
+        if (slot >= (1LL << 31) - 4096)
+            return fail(PBVD_ENOTSUP, "D + 2L too large for the survivor buffer of one wave (%lld bytes)",
+                        (long long)slot);
+    }
     const int idx = find_code(c);
     if (idx < 0) return fail(PBVD_ENOTSUP, "no kernel compiled for this generator set");
 
@@ -277,7 +286,8 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
     (void)hipGetLastError();
     p->ndw = pbvd::survivor_row_dwords(c.K);
     p->row_stages = pbvd::survivor_row_stages(c.K);
-    const int64_t rows = ceil_div((int64_t)c.D + c.L, p->row_stages) + 1;
+    // every forward stage of a PB (at most D + 2L) is stored
+    const int64_t rows = ceil_div((int64_t)c.D + 2 * (int64_t)c.L, p->row_stages) + 1;
     p->sp_wave_dwords = ceil_div(rows * pbvd::kWave * p->ndw, 64) * 64;
     int64_t mb = 8192;
     if (const char *env = getenv("PBVD_WORKSPACE_MB")) {
@@ -362,6 +372,7 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     v.K = p->code.K;
     v.D = p->code.D;
     v.L = p->code.L;
+    v.byte_perm = (p->code.pm_bits == 16 && p->code.K >= 6) ? 1 : 0;
     hipError_t e = pbvd::unpack_survivors(v, d_dec, s);
     if (e != hipSuccess) return fail_hip(e, "survivor expansion launch");
     e = hipStreamSynchronize(s);

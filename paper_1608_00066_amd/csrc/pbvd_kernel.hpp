@@ -32,6 +32,10 @@
 
 #include <type_traits>
 
+// Lambdas on the hot path are forced inline so that the arrays they capture
+// stay in registers.
+#define PBVD_INLINE_LAMBDA __attribute__((always_inline))
+
 namespace pbvd {
 
 constexpr int kWave = 64;
@@ -105,20 +109,25 @@ __host__ __device__ constexpr int rotl_v(int u, int s) {
     return rotr_v<V>(u, (V - s) % V);
 }
 
-// Bit position, inside the survivor word group of one stage, of the
-// decision of the state whose rotated index is u.  Inverse-free: maps u's
-// bit t to bit pos_of_ubit(t).
-template <int V>
-__host__ __device__ constexpr int pos_of_ubit(int t) {
+// Survivor bit layout of one stage.  The decision of the state whose
+// rotated index is u (register r = u mod N/2, half h = u >> (K-2)) sits at a
+// bit position obtained by moving each bit t of u to ubit_pos(t):
+//   shift layout (BP = false): dword r >> 4, bit (r & 15) + 16 h;
+//   byte-permute layout (BP = true, 16-bit metrics, N >= 32): dword r >> 4,
+//     bit 16 (r & 1) + 8 h + ((r & 15) >> 1) -- the sign bytes of two
+//     registers' differences are gathered with one v_perm_b32 and eight
+//     such words are merged per dword.
+// Several stages share a dword when N < 32 (shift layout only).
+template <int V, bool BP>
+__host__ __device__ constexpr int ubit_pos(int t) {
+    if (BP) return t == 0 ? 4 : (t < 4 ? t - 1 : (t == V - 1 ? 3 : t + 1));
     return t == V - 1 ? 4 : (t < 4 ? t : t + 1);
 }
-template <int V>
+template <int V, bool BP>
 __device__ __forceinline__ uint32_t u_to_idx(uint32_t u) {
-    constexpr int lowbits = (V - 1) < 4 ? (V - 1) : 4;
-    uint32_t low = u & ((1u << lowbits) - 1u);
-    uint32_t half = (u >> (V - 1)) & 1u;
-    uint32_t idx = low | (half << 4);
-    if constexpr (V - 1 > 4) idx |= ((u >> 4) & ((1u << (V - 1 - 4)) - 1u)) << 5;
+    uint32_t idx = 0;
+#pragma unroll
+    for (int t = 0; t < V; ++t) idx |= ((u >> t) & 1u) << ubit_pos<V, BP>(t);
     return idx;
 }
 
@@ -145,6 +154,10 @@ struct PM16 {
         v2u d = __builtin_bit_cast(v2u, sub(b, a));
         d = d >> (v2u){15, 15};
         return __builtin_bit_cast(uint32_t, d);
+    }
+    // raw b - a of both halves: their sign bits are bits 15 and 31
+    static __device__ __forceinline__ uint32_t diff(T a, T b) {
+        return __builtin_bit_cast(uint32_t, sub(b, a));
     }
     static __device__ __forceinline__ int lo(T a) { return a.x; }
     static __device__ __forceinline__ int hi(T a) { return a.y; }
@@ -176,6 +189,59 @@ __device__ __forceinline__ uint32_t shl_or(uint32_t x, uint32_t acc) {
     return r;
 }
 
+// acc | (x & mask) as one v_and_or_b32 (mask in an SGPR).
+__device__ __forceinline__ uint32_t and_or(uint32_t x, uint32_t mask, uint32_t acc) {
+    uint32_t r;
+    asm("v_and_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "s"(mask), "v"(acc));
+    return r;
+}
+
+// Survivor rows of one wave slot, addressed through a buffer resource: the
+// row offset is wave-uniform (SGPR), the lane offset a loop-invariant VGPR,
+// so no per-stage address arithmetic runs on the vector unit.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+
+template <int NDW>
+struct RowStore {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;  // bytes
+    static constexpr int kRowBytes = kWave * NDW * 4;
+    __device__ __forceinline__ void store(int row, const uint32_t (&v)[NDW]) const {
+        const int so = row * kRowBytes;
+        if constexpr (NDW == 1) {
+            __builtin_amdgcn_raw_buffer_store_b32(v[0], rsrc, lane_off, so, 0);
+        } else if constexpr (NDW == 2) {
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{v[0], v[1]}, rsrc, lane_off, so, 0);
+        } else {
+#pragma unroll
+            for (int w = 0; w < NDW; w += 4)
+                __builtin_amdgcn_raw_buffer_store_b128(u32x4{v[w], v[w + 1], v[w + 2], v[w + 3]}, rsrc,
+                                                       lane_off + 4 * w, so, 0);
+        }
+    }
+    __device__ __forceinline__ void load(int row, uint32_t (&v)[NDW]) const {
+        const int so = row * kRowBytes;
+        if constexpr (NDW == 1) {
+            v[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane_off, so, 0);
+        } else if constexpr (NDW == 2) {
+            const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane_off, so, 0);
+            v[0] = t.x;
+            v[1] = t.y;
+        } else {
+#pragma unroll
+            for (int w = 0; w < NDW; w += 4) {
+                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rsrc, lane_off + 4 * w, so, 0);
+                v[w] = t.x;
+                v[w + 1] = t.y;
+                v[w + 2] = t.z;
+                v[w + 3] = t.w;
+            }
+        }
+    }
+};
+
 enum { kSoftI8 = 0, kHardU8 = 1 };
 
 template <int KIND>
@@ -202,9 +268,10 @@ __device__ __forceinline__ void code_word_metrics(const int (&q)[R], int (&bm)[1
 
 // ---------------------------------------------------------------------------
 // One trellis stage at compile-time phase PH.  Writes the stage's decision
-// bits into dw[] at slot offset SLOT0 (in units of packed registers).
+// bits into dw[] at slot offset SLOT0 (in units of packed registers) in the
+// shift layout, or in the byte-permute layout when BP.
 // ---------------------------------------------------------------------------
-template <class C, class P, int PH, int SLOT0, int NDW>
+template <class C, class P, int PH, int SLOT0, int NDW, bool BP>
 __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int (&q)[C::R],
                                           uint32_t (&dw)[NDW]) {
     using T = typename P::T;
@@ -214,13 +281,31 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
     int bm[NC];
     code_word_metrics<C::R>(q, bm);
 
+    // decisions of register X (two per register: lower and upper half)
+    uint32_t dd[NR];
+    auto record = [&](auto xc, T a, T b) PBVD_INLINE_LAMBDA {
+        constexpr int X = decltype(xc)::value;
+        if constexpr (!BP) {
+            constexpr int sx = SLOT0 + X;
+            dw[sx >> 4] = shl_or<(sx & 15)>(P::dec(a, b), dw[sx >> 4]);
+        } else {
+            dd[X] = P::diff(a, b);
+            if constexpr (X & 1) {
+                // sign bytes of registers X-1 and X: [lo(X-1), hi(X-1), lo(X), hi(X)]
+                const uint32_t p = __builtin_amdgcn_perm(dd[X], dd[X - 1], 0x07050301u);
+                constexpr int kk = (X & 15) >> 1;
+                dw[X >> 4] = and_or(p >> (7 - kk), 0x01010101u << kk, dw[X >> 4]);
+            }
+        }
+    };
+
     if constexpr (PH < V - 1) {
         // pairs (X, Y = X | 2^PH); halves differ in state bit V-1-PH
         constexpr int GP = C::gcol(V - 1 - PH);
         T pair[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) pair[c] = P::make(bm[c], bm[c ^ GP]);
-        static_for<0, NR / 2>([&](auto kc) {
+        static_for<0, NR / 2>([&](auto kc) PBVD_INLINE_LAMBDA {
             constexpr int k = decltype(kc)::value;
             constexpr int X = ((k >> PH) << (PH + 1)) | (k & ((1 << PH) - 1));
             constexpr int Y = X | (1 << PH);
@@ -231,9 +316,8 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
             const T b1 = P::add(pm[Y], pair[alpha ^ G0 ^ GK]);
             pm[X] = P::vmin(a0, b0);
             pm[Y] = P::vmin(a1, b1);
-            constexpr int sx = SLOT0 + X, sy = SLOT0 + Y;
-            dw[sx >> 4] = shl_or<(sx & 15)>(P::dec(a0, b0), dw[sx >> 4]);
-            dw[sy >> 4] = shl_or<(sy & 15)>(P::dec(a1, b1), dw[sy >> 4]);
+            record(std::integral_constant<int, X>{}, a0, b0);
+            record(std::integral_constant<int, Y>{}, a1, b1);
             return true;
         });
     } else {
@@ -241,14 +325,13 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
         T pair[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) pair[c] = P::make(bm[c], bm[c ^ GK]);
-        static_for<0, NR>([&](auto xc) {
+        static_for<0, NR>([&](auto xc) PBVD_INLINE_LAMBDA {
             constexpr int X = decltype(xc)::value;
             constexpr int alpha = C::out0(2 * X);
             const T a = P::add(P::bcast_lo(pm[X]), pair[alpha]);
             const T b = P::add(P::bcast_hi(pm[X]), pair[alpha ^ G0]);
             pm[X] = P::vmin(a, b);
-            constexpr int sx = SLOT0 + X;
-            dw[sx >> 4] = shl_or<(sx & 15)>(P::dec(a, b), dw[sx >> 4]);
+            record(xc, a, b);
             return true;
         });
     }
@@ -264,6 +347,9 @@ struct Layout {
     static constexpr int S = NR >= 16 ? 1 : 16 / NR;      // stages per stored row
     static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
     static constexpr int U = V / gcd(V, S) * S;           // unrolled stages per loop trip
+    static constexpr bool kBytePerm = std::is_same<P, PM16>::value && NR >= 16;
+    // a second, check-free copy of the loop trip only where it is small
+    static constexpr bool kFastLoop = NR <= 32;
     // Largest metric spread: the known-state start (8192) plus K-1 stages of
     // the widest branch-metric difference (128 per symbol).  Between two
     // renormalizations every metric moves by at most 128*R per stage.
@@ -277,11 +363,6 @@ struct Layout {
 template <int V>
 __device__ __forceinline__ int rotr_rt(int u, int s) {
     return ((u >> s) | (u << (V - s))) & ((1 << V) - 1);
-}
-
-template <int V>
-__device__ __forceinline__ int ubit_pos_rt(int t) {
-    return t == V - 1 ? 4 : (t < 4 ? t : t + 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -343,8 +424,11 @@ __global__ void __launch_bounds__(256)
     const int i_store0 = (int)(d0w - f0w);    // first stored / traced stage
     const int i_dec_end = (int)(d1w - f0w);   // end of the decoded range
     const uint8_t *in = a.syms + (f0w + lane_stage_off) * R;
-    uint32_t *spw = a.sp + wave_local * a.sp_wave_dwords;
-    const int k0 = i_store0 / S;              // first stored row
+    RowStore<LY::NDW> rows;
+    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
+                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
+    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
+    const int k0 = i_store0 / S;              // first row the traceback reads
 
     // ---- initial metrics ----
     T pm[NR];
@@ -366,12 +450,34 @@ __global__ void __launch_bounds__(256)
     constexpr int NW = (NB + 3) / 4;   // dwords holding the trip's symbols
     constexpr int ND = NW + 1;         // dwords fetched (unaligned start)
     const uint8_t *const in_end = a.syms + a.T * R;
-    auto fetch = [&](uint32_t (&raw)[ND], uint32_t &sh, int i0) {
+    // Wave-uniform: every wide fetch of every lane stays inside the input.
+    // Only the last wave(s) of a stream take the byte-load path.
+    const int64_t far_lane = wave < a.n_int_waves
+                                 ? (a.b_hi - 1 - (a.b_lo + wave * kWave) < kWave - 1
+                                        ? a.b_hi - 1 - (a.b_lo + wave * kWave)
+                                        : kWave - 1)
+                                 : 0;
+    const bool fetch_safe =
+        a.syms + (f0w + far_lane * D + (len - 1)) * R + 4 * ND <= in_end;
+    // last trip start whose wide fetch stays inside the input for every lane
+    const int64_t safe_bytes = (int64_t)(in_end - (a.syms + (f0w + far_lane * D) * R)) - 4 * ND;
+    const int i_safe = safe_bytes < 0 ? -1 : (safe_bytes / R > len ? len : (int)(safe_bytes / R));
+    // when a trip spans whole dwords the lane's misalignment never changes
+    const uint32_t mis0 = (uint32_t)((uintptr_t)in & 3u);
+    const uint8_t *const in_aligned = in - mis0;  // keeps the global address space
+    auto fetch = [&](uint32_t (&raw)[ND], uint32_t &sh, int i0, bool wide) PBVD_INLINE_LAMBDA {
         const uint8_t *p = in + (int64_t)i0 * R;
-        const uint32_t mis = (uint32_t)((uintptr_t)p & 3u);
-        const uint8_t *pa = p - mis;  // pointer arithmetic keeps the global address space
+        uint32_t mis;
+        const uint8_t *pa;
+        if constexpr (NB % 4 == 0) {
+            mis = mis0;
+            pa = in_aligned + (int64_t)i0 * R;
+        } else {
+            mis = (uint32_t)((uintptr_t)p & 3u);
+            pa = p - mis;
+        }
         sh = mis * 8u;
-        if (pa + 4 * ND <= in_end) {
+        if (wide) {
             const uint32_t *q = reinterpret_cast<const uint32_t *>(pa);
 #pragma unroll
             for (int j = 0; j < ND; ++j) raw[j] = q[j];
@@ -405,43 +511,59 @@ __global__ void __launch_bounds__(256)
     uint32_t raw_next[ND], sh_next, wsym[NW];
     {
         uint32_t raw0[ND], sh0;
-        fetch(raw0, sh0, 0);
+        fetch(raw0, sh0, 0, fetch_safe);
         align_trip(raw0, sh0, wsym);
     }
     uint32_t dw[NDW];
 #pragma unroll
     for (int w = 0; w < NDW; ++w) dw[w] = 0;
     int trips_since_renorm = 0;
-    for (int i0 = 0;; i0 += U) {
+    int i0 = 0;
+    if constexpr (LY::kFastLoop) {
+        // Straight-line trips: whole trips whose next fetch is in bounds need
+        // no per-stage checks; the generic loop below finishes the stream.
+        const int fast_end = len - U < i_safe - U ? len - U : i_safe - U;
+        for (; i0 < fast_end; i0 += U) {
+            fetch(raw_next, sh_next, i0 + U, true);
+            if (++trips_since_renorm == LY::kRenormTrips) {
+                trips_since_renorm = 0;
+                const T ref = P::bcast_lo(pm[0]);
+#pragma unroll
+                for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
+            }
+            static_for<0, U>([&](auto kc) PBVD_INLINE_LAMBDA {
+                constexpr int k = decltype(kc)::value;
+                int q[R];
+                symbols(wsym, k, q);
+                acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm>(pm, q, dw);
+                if constexpr ((k % S) == S - 1) {
+                    rows.store((i0 + k) / S, dw);
+#pragma unroll
+                    for (int w = 0; w < NDW; ++w) dw[w] = 0;
+                }
+                return true;
+            });
+            align_trip(raw_next, sh_next, wsym);
+        }
+    }
+    for (;; i0 += U) {
         const bool last_trip = i0 + U >= len;
-        if (!last_trip) fetch(raw_next, sh_next, i0 + U);
+        if (!last_trip) fetch(raw_next, sh_next, i0 + U, fetch_safe);
         if (++trips_since_renorm == LY::kRenormTrips) {
             trips_since_renorm = 0;
             const T ref = P::bcast_lo(pm[0]);
 #pragma unroll
             for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
         }
-        const bool more = static_for<0, U>([&](auto kc) {
+        const bool more = static_for<0, U>([&](auto kc) PBVD_INLINE_LAMBDA {
             constexpr int k = decltype(kc)::value;
             if (i0 + k >= len) return false;
             int q[R];
             symbols(wsym, k, q);
-            acs_stage<C, P, k % V, (k % S) * NR, NDW>(pm, q, dw);
+            acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm>(pm, q, dw);
             if ((k % S) == S - 1 || i0 + k + 1 == len) {
                 const int row = (i0 + k) / S;
-                if (row >= k0) {
-                    uint32_t *dst = spw + ((int64_t)(row - k0) * kWave + lane) * NDW;
-                    if constexpr (NDW == 1) {
-                        dst[0] = dw[0];
-                    } else if constexpr (NDW == 2) {
-                        *reinterpret_cast<uint2 *>(dst) = make_uint2(dw[0], dw[1]);
-                    } else {
-#pragma unroll
-                        for (int w = 0; w < NDW; w += 4)
-                            *reinterpret_cast<uint4 *>(dst + w) =
-                                make_uint4(dw[w], dw[w + 1], dw[w + 2], dw[w + 3]);
-                    }
-                }
+                rows.store(row, dw);
 #pragma unroll
                 for (int w = 0; w < NDW; ++w) dw[w] = 0;
             }
@@ -471,7 +593,7 @@ __global__ void __launch_bounds__(256)
                 if (P::lo(pm[r]) == m && s_lo < best) best = s_lo;
                 if (P::hi(pm[r]) == m && s_hi < best) best = s_hi;
             }
-            idx = u_to_idx<V>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
+            idx = u_to_idx<V, LY::kBytePerm>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
         }
         if (a.final_pm && active) {
             int32_t *fp = a.final_pm + (b - a.pb_first) * N;
@@ -499,29 +621,13 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int t = 0; t < TBR; ++t) {
             const int row = top - t < row_lo ? row_lo : top - t;
-            const uint32_t *src = spw + ((int64_t)(row - row_lo) * kWave + lane) * NDW;
-            if constexpr (NDW == 1) {
-                dst[t][0] = src[0];
-            } else if constexpr (NDW == 2) {
-                const uint2 v = *reinterpret_cast<const uint2 *>(src);
-                dst[t][0] = v.x;
-                dst[t][1] = v.y;
-            } else {
-#pragma unroll
-                for (int w = 0; w < NDW; w += 4) {
-                    const uint4 v = *reinterpret_cast<const uint4 *>(src + w);
-                    dst[t][w] = v.x;
-                    dst[t][w + 1] = v.y;
-                    dst[t][w + 2] = v.z;
-                    dst[t][w + 3] = v.w;
-                }
-            }
+            rows.load(row, dst[t]);
         }
     };
 
     // one traceback step at stage i with that stage's survivor row
     auto step = [&](int i, const uint32_t (&row)[NDW], int sub) {
-        const int qpos = ubit_pos_rt<V>(ph);
+        const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
         const uint32_t x = (idx >> qpos) & 1u;
         if (i < i_dec_end) {
             word = (word << 1) | x;
@@ -575,11 +681,11 @@ __global__ void __launch_bounds__(256)
 
     // trace rows top..top-TBR+1; false once the first stored stage is passed
     auto run_block = [&](const uint32_t (&blk)[TBR][NDW], int top) {
-        return static_for<0, TBR>([&](auto tc) {
+        return static_for<0, TBR>([&](auto tc) PBVD_INLINE_LAMBDA {
             constexpr int t = decltype(tc)::value;
             const int row = top - t;
             if (row < row_lo) return false;
-            return static_for<0, S>([&](auto sc) {
+            return static_for<0, S>([&](auto sc) PBVD_INLINE_LAMBDA {
                 constexpr int sub = S - 1 - decltype(sc)::value;
                 const int i = row * S + sub;
                 if (i >= len) return true;
