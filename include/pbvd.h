@@ -148,6 +148,56 @@ pbvd_status pbvd_debug_branch_metrics(pbvd_plan *p, const void *d_syms, int64_t 
 /* Free the plan and its device workspace (synchronizes the device). */
 void pbvd_destroy(pbvd_plan *p);
 
+/* ---- Batched decoding: many independent frames, several codes ----------
+ *
+ * A batch decodes many frames (each a separate stream in the sense of
+ * Sec. III-A: its own PBs, its own start and end) in one launch per code.
+ * The PBs of all frames of a code are packed 64 to a wave regardless of
+ * frame boundaries, so thousands of short frames fill the GPU as well as one
+ * long stream does.  Every frame's output is identical to decoding that
+ * frame alone with pbvd_decode and the same code parameters. */
+
+typedef struct pbvd_batch pbvd_batch;
+
+typedef struct {
+    int64_t sym_offset; /* byte offset in d_syms of the frame's first symbol;
+                           the frame has (n_bits + terminated*(K-1)) * R bytes */
+    int64_t n_bits;     /* information bits of the frame, >= 1 */
+    int64_t out_offset; /* byte offset in d_out of the frame's ceil(n_bits/8)
+                           output bytes (same bit order as pbvd_decode) */
+    int32_t code;       /* index into the codes given to pbvd_batch_create */
+    int32_t reserved;   /* must be 0 */
+} pbvd_frame;
+
+/* Create a batch decoder for n_codes (1..16) code/block parameter sets.
+ * Each must be valid for pbvd_create and have D % 8 == 0 (decoded blocks
+ * start on byte boundaries). */
+pbvd_status pbvd_batch_create(const pbvd_code *codes, int32_t n_codes, pbvd_batch **out);
+
+/* Describe the frames (host array) of the next decodes: builds the work list
+ * (PBs of all frames, grouped by code, longest first, 64 per wave), uploads
+ * it and sizes the device workspace.  sym_bytes / out_bytes are the sizes of
+ * the device buffers later passed to pbvd_batch_decode; every frame must lie
+ * inside them and output ranges must not overlap.  Synchronous (blocks the
+ * calling thread); PBVD_EINVAL on a bad frame (nothing is changed). */
+pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64_t n_frames,
+                                  int64_t sym_bytes, int64_t out_bytes);
+
+/* Decode the frames last given to pbvd_batch_set_frames: one kernel launch
+ * per code, asynchronous on hip_stream.  It allocates nothing and copies
+ * nothing from the host, so it can be captured in a HIP graph and replayed.
+ * Bytes of d_out outside the frames' output ranges are not written. */
+pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out, void *hip_stream);
+
+/* Work-list statistics of the current frames: tiles (waves), parallel blocks,
+ * forward stages summed over PBs, and device workspace bytes; any pointer may
+ * be NULL. */
+pbvd_status pbvd_batch_info(const pbvd_batch *b, int64_t *n_tiles, int64_t *n_blocks,
+                            int64_t *n_forward_stages, int64_t *workspace_bytes);
+
+/* Free the batch and its device memory (synchronizes the device). */
+void pbvd_batch_destroy(pbvd_batch *b);
+
 /* Static description of a status code. */
 const char *pbvd_strerror(pbvd_status s);
 

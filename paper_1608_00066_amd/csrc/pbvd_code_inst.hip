@@ -43,6 +43,29 @@ hipError_t launch_code(const LaunchRequest &req) {
     return hipErrorInvalidValue;
 }
 
+template <class C, class P, int KIND>
+static hipError_t launch_tiles_one(const TileLaunchRequest &req) {
+    hipLaunchKernelGGL((decode_tiles_kernel<C, P, KIND>), dim3(req.grid), dim3(kBlockThreads), 0,
+                       req.stream, req.args);
+    return hipGetLastError();
+}
+
+template <int IDX>
+hipError_t launch_tiles(const TileLaunchRequest &req) {
+    using C = typename CodeAt<IDX>::type;
+    if (req.pm_bits == 16) {
+        return req.input_kind == kHardU8 ? launch_tiles_one<C, PM16, kHardU8>(req)
+                                         : launch_tiles_one<C, PM16, kSoftI8>(req);
+    }
+    if constexpr (C::K <= 8) {
+        if (req.pm_bits == 32)
+            return req.input_kind == kHardU8 ? launch_tiles_one<C, PM32, kHardU8>(req)
+                                             : launch_tiles_one<C, PM32, kSoftI8>(req);
+    }
+    return hipErrorInvalidValue;
+}
+
 template hipError_t launch_code<PBVD_CODE_IDX>(const LaunchRequest &req);
+template hipError_t launch_tiles<PBVD_CODE_IDX>(const TileLaunchRequest &req);
 
 }  // namespace pbvd

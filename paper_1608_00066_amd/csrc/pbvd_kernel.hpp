@@ -366,76 +366,52 @@ __device__ __forceinline__ int rotr_rt(int u, int s) {
 }
 
 // ---------------------------------------------------------------------------
-// The decoder kernel: forward ACS with survivor stores, final metrics, then
-// traceback with packed output, for every PB of the launch.
+// Decode body shared by the stream kernel and the batch (tile) kernel:
+// forward ACS with survivor-row stores, final metrics, then traceback with
+// packed output, for the 64 PBs of one wave.
 // ---------------------------------------------------------------------------
-// Register target for the 256-state trellis (waves per SIMD the compiler
-// must leave room for).  Two waves force scratch spills inside the stage
-// loop, which measured 2x slower than one wave with accumulator-register
-// spills.
-#ifndef PBVD_BIG_TRELLIS_WAVES_PER_EU
-#define PBVD_BIG_TRELLIS_WAVES_PER_EU 1
-#endif
+enum { kOutDirect = 0, kOutAtomic = 1, kOutBytes = 2 };
 
-template <class C, class P, int KIND>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
-    decode_kernel(const KernelArgs a) {
+struct WaveJob {
+    // wave-uniform
+    int len;             // forward stages the wave runs (the longest lane's)
+    int store0_min;      // lowest first-traced stage over the lanes
+    int i_safe;          // last trip start whose wide fetch is in bounds (-1: none)
+    bool fetch_safe;     // every wide fetch of the wave stays in bounds
+    bool need_final;     // some lane needs its final metrics
+    int out_mode;        // kOutDirect / kOutAtomic / kOutBytes
+    const uint8_t *in_end;
+    uint8_t *out;
+    int64_t out_bytes;   // kOutDirect bound
+    uint32_t *out_words; // kOutAtomic staging
+    // per lane
+    const uint8_t *in;   // symbols of the lane's first forward stage
+    int my_len, my_store0, my_dec_end;
+    bool known;          // start from encoder state 0
+    bool argmin;         // trace back from the least-metric state
+    bool active;
+    int64_t out_bit0;    // output bit position of the lane's first decoded bit
+    int32_t *pm_out;     // final-metric row or null
+};
+
+// VARLEN: lanes may run fewer stages than the wave (batch tiles).  All lanes
+// start at stage 0 with their own initial metrics; a lane's stages past its
+// own end compute values nobody reads, and its traceback starts at its own
+// last stage.
+template <class C, class P, int KIND, bool VARLEN>
+__device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Layout<C, P>::NDW> &rows) {
     using T = typename P::T;
     using LY = Layout<C, P>;
     constexpr int V = C::V, N = C::N, NR = C::NR, R = C::R;
     constexpr int NDW = LY::NDW, S = LY::S, U = LY::U;
-
-    const int lane = threadIdx.x & (kWave - 1);
-    // wave index made provably uniform so that all geometry stays scalar
-    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
-                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (wave_local >= a.n_waves) return;
-    const int64_t wave = a.wave_begin + wave_local;
-    const int64_t D = a.D, L = a.L;
-
-    // ---- block geometry (Sec. III-A with M = L, clipped to the stream) ----
-    int64_t b, f0w, f1w, d0w, d1w;   // wave-uniform PB geometry (interior: lane 0's)
-    bool active;
-    int64_t lane_stage_off;           // this lane's stage offset from f0w
-    if (wave < a.n_int_waves) {
-        const int64_t bw = a.b_lo + wave * kWave;
-        b = bw + lane;
-        active = b < a.b_hi;
-        lane_stage_off = (active ? (int64_t)lane : (a.b_hi - 1 - bw)) * D;
-        if (!active) b = a.b_hi - 1;
-        d0w = bw * D;
-        f0w = d0w - L;
-        f1w = d0w + D + L;
-        d1w = d0w + D;
-    } else {
-        const int64_t e = wave - a.n_int_waves;
-        b = e < a.n_head ? a.pb_first + e : a.b_hi + (e - a.n_head);
-        active = lane == 0;
-        lane_stage_off = 0;
-        d0w = b * D;
-        f0w = d0w - L < 0 ? 0 : d0w - L;
-        f1w = d0w + D + L > a.T ? a.T : d0w + D + L;
-        d1w = d0w + D > a.n ? a.n : d0w + D;
-    }
-    // stage counts fit in 32 bits (at most D + 2L), which keeps the loop
-    // control on the scalar unit
-    const int len = (int)(f1w - f0w);         // forward stages
-    const int i_store0 = (int)(d0w - f0w);    // first stored / traced stage
-    const int i_dec_end = (int)(d1w - f0w);   // end of the decoded range
-    const uint8_t *in = a.syms + (f0w + lane_stage_off) * R;
-    RowStore<LY::NDW> rows;
-    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
-                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
-    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
-    const int k0 = i_store0 / S;              // first row the traceback reads
+    const int len = j.len;
+    const uint8_t *const in = j.in;
 
     // ---- initial metrics ----
     T pm[NR];
     {
-        // known start state 0 when this lane's forward range starts at stage 0
-        // (an interior PB can, when L is a multiple of D)
-        const int big = f0w + lane_stage_off == 0 ? 8192 : 0;
+        // known start state 0 when the lane's forward range starts at stage 0
+        const int big = j.known ? 8192 : 0;
 #pragma unroll
         for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? 0 : big, big);
     }
@@ -449,23 +425,14 @@ __global__ void __launch_bounds__(256)
     constexpr int NB = U * R;
     constexpr int NW = (NB + 3) / 4;   // dwords holding the trip's symbols
     constexpr int ND = NW + 1;         // dwords fetched (unaligned start)
-    const uint8_t *const in_end = a.syms + a.T * R;
-    // Wave-uniform: every wide fetch of every lane stays inside the input.
-    // Only the last wave(s) of a stream take the byte-load path.
-    const int64_t far_lane = wave < a.n_int_waves
-                                 ? (a.b_hi - 1 - (a.b_lo + wave * kWave) < kWave - 1
-                                        ? a.b_hi - 1 - (a.b_lo + wave * kWave)
-                                        : kWave - 1)
-                                 : 0;
-    const bool fetch_safe =
-        a.syms + (f0w + far_lane * D + (len - 1)) * R + 4 * ND <= in_end;
-    // last trip start whose wide fetch stays inside the input for every lane
-    const int64_t safe_bytes = (int64_t)(in_end - (a.syms + (f0w + far_lane * D) * R)) - 4 * ND;
-    const int i_safe = safe_bytes < 0 ? -1 : (safe_bytes / R > len ? len : (int)(safe_bytes / R));
+    const uint8_t *const in_end = j.in_end;
+    // a lane never fetches past its own last trip
+    const int my_last_trip = VARLEN ? ((j.my_len - 1) / U) * U : 0;
     // when a trip spans whole dwords the lane's misalignment never changes
     const uint32_t mis0 = (uint32_t)((uintptr_t)in & 3u);
     const uint8_t *const in_aligned = in - mis0;  // keeps the global address space
     auto fetch = [&](uint32_t (&raw)[ND], uint32_t &sh, int i0, bool wide) PBVD_INLINE_LAMBDA {
+        if constexpr (VARLEN) i0 = i0 < my_last_trip ? i0 : my_last_trip;
         const uint8_t *p = in + (int64_t)i0 * R;
         uint32_t mis;
         const uint8_t *pa;
@@ -480,26 +447,26 @@ __global__ void __launch_bounds__(256)
         if (wide) {
             const uint32_t *q = reinterpret_cast<const uint32_t *>(pa);
 #pragma unroll
-            for (int j = 0; j < ND; ++j) raw[j] = q[j];
+            for (int jj = 0; jj < ND; ++jj) raw[jj] = q[jj];
         } else {
 #pragma unroll
-            for (int j = 0; j < ND; ++j) {
+            for (int jj = 0; jj < ND; ++jj) {
                 uint32_t v = 0;
 #pragma unroll
                 for (int bb = 0; bb < 4; ++bb) {
-                    const uint8_t *c = pa + 4 * j + bb;
+                    const uint8_t *c = pa + 4 * jj + bb;
                     if (c >= p && c < in_end) v |= (uint32_t)*c << (8 * bb);
                 }
-                raw[j] = v;
+                raw[jj] = v;
             }
         }
     };
-    auto align_trip = [&](const uint32_t (&raw)[ND], uint32_t sh, uint32_t (&w)[NW]) {
+    auto align_trip = [&](const uint32_t (&raw)[ND], uint32_t sh, uint32_t (&w)[NW]) PBVD_INLINE_LAMBDA {
 #pragma unroll
-        for (int j = 0; j < NW; ++j)
-            w[j] = (uint32_t)(((uint64_t)raw[j + 1] << 32 | raw[j]) >> sh);
+        for (int jj = 0; jj < NW; ++jj)
+            w[jj] = (uint32_t)(((uint64_t)raw[jj + 1] << 32 | raw[jj]) >> sh);
     };
-    auto symbols = [&](const uint32_t (&w)[NW], int k, int (&q)[R]) {
+    auto symbols = [&](const uint32_t (&w)[NW], int k, int (&q)[R]) PBVD_INLINE_LAMBDA {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int t = k * R + r;
@@ -511,7 +478,7 @@ __global__ void __launch_bounds__(256)
     uint32_t raw_next[ND], sh_next, wsym[NW];
     {
         uint32_t raw0[ND], sh0;
-        fetch(raw0, sh0, 0, fetch_safe);
+        fetch(raw0, sh0, 0, j.fetch_safe);
         align_trip(raw0, sh0, wsym);
     }
     uint32_t dw[NDW];
@@ -521,8 +488,8 @@ __global__ void __launch_bounds__(256)
     int i0 = 0;
     if constexpr (LY::kFastLoop) {
         // Straight-line trips: whole trips whose next fetch is in bounds need
-        // no per-stage checks; the generic loop below finishes the stream.
-        const int fast_end = len - U < i_safe - U ? len - U : i_safe - U;
+        // no per-stage checks; the generic loop below finishes the block.
+        const int fast_end = len - U < j.i_safe - U ? len - U : j.i_safe - U;
         for (; i0 < fast_end; i0 += U) {
             fetch(raw_next, sh_next, i0 + U, true);
             if (++trips_since_renorm == LY::kRenormTrips) {
@@ -548,7 +515,7 @@ __global__ void __launch_bounds__(256)
     }
     for (;; i0 += U) {
         const bool last_trip = i0 + U >= len;
-        if (!last_trip) fetch(raw_next, sh_next, i0 + U, fetch_safe);
+        if (!last_trip) fetch(raw_next, sh_next, i0 + U, j.fetch_safe);
         if (++trips_since_renorm == LY::kRenormTrips) {
             trips_since_renorm = 0;
             const T ref = P::bcast_lo(pm[0]);
@@ -562,8 +529,7 @@ __global__ void __launch_bounds__(256)
             symbols(wsym, k, q);
             acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm>(pm, q, dw);
             if ((k % S) == S - 1 || i0 + k + 1 == len) {
-                const int row = (i0 + k) / S;
-                rows.store(row, dw);
+                rows.store((i0 + k) / S, dw);
 #pragma unroll
                 for (int w = 0; w < NDW; ++w) dw[w] = 0;
             }
@@ -575,17 +541,16 @@ __global__ void __launch_bounds__(256)
 
     // ---- final metrics and traceback start (Sec. III-A; Sec. II at an
     //      unterminated stream end) ----
-    const int ph_end = (int)(len % V);
-    const bool argmin_start = f1w == a.T && !a.terminated;
+    const int ph_end = len % V;
     uint32_t idx = 0;  // rotated index of state 0 is 0
-    if (argmin_start || a.final_pm) {
+    if (j.need_final) {
         int m = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             m = min(m, P::lo(pm[r]));
             m = min(m, P::hi(pm[r]));
         }
-        if (argmin_start) {
+        if (j.argmin) {
             int best = N;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
@@ -595,8 +560,8 @@ __global__ void __launch_bounds__(256)
             }
             idx = u_to_idx<V, LY::kBytePerm>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
         }
-        if (a.final_pm && active) {
-            int32_t *fp = a.final_pm + (b - a.pb_first) * N;
+        if (j.pm_out && j.active) {
+            int32_t *fp = j.pm_out;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
                 fp[rotr_rt<V>(r, ph_end)] = P::lo(pm[r]) - m;
@@ -610,14 +575,14 @@ __global__ void __launch_bounds__(256)
     // blocks of TBR rows are loaded one block ahead of their use; only the
     // bit selection inside a row follows the state.
     constexpr int TBR = NDW >= 4 ? 4 : (NDW == 2 ? 8 : (16 / S));  // <= 16 stages, <= 32 dwords per block
-    const int row_lo = k0;
+    const int i_lo = j.store0_min;
+    const int row_lo = i_lo / S;
     const int row_hi = (len - 1) / S;
-    const int64_t out_bit0 = (b - a.pb_first) * D;
-    const int n_dec = i_dec_end - i_store0;
+    const int n_dec = j.my_dec_end - j.my_store0;
     uint32_t word = 0;
     int ph = (len - 1) % V;  // input phase of the stage being traced
 
-    auto load_block = [&](uint32_t (&dst)[TBR][NDW], int top) {
+    auto load_block = [&](uint32_t (&dst)[TBR][NDW], int top) PBVD_INLINE_LAMBDA {
 #pragma unroll
         for (int t = 0; t < TBR; ++t) {
             const int row = top - t < row_lo ? row_lo : top - t;
@@ -625,62 +590,75 @@ __global__ void __launch_bounds__(256)
         }
     };
 
-    // one traceback step at stage i with that stage's survivor row
-    auto step = [&](int i, const uint32_t (&row)[NDW], int sub) {
-        const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
-        const uint32_t x = (idx >> qpos) & 1u;
-        if (i < i_dec_end) {
-            word = (word << 1) | x;
-            const int rel = i - i_store0;
-            if ((rel & 31) == 0) {
-                const int m = n_dec - rel < 32 ? n_dec - rel : 32;
-                const int64_t bitpos = out_bit0 + rel;
-                if (active) {
-                    if (a.direct_out) {
-                        const int64_t byte = bitpos >> 3;
-                        if (m == 32 && byte + 4 <= a.out_bytes) {
-                            *reinterpret_cast<uint32_t *>(a.out + byte) = word;
-                        } else {
-                            for (int bb = 0; bb < ((m + 7) >> 3); ++bb)
-                                if (byte + bb < a.out_bytes) a.out[byte + bb] = (uint8_t)(word >> (8 * bb));
-                        }
-                    } else {
-                        const uint32_t sh = (uint32_t)(bitpos & 31);
-                        uint32_t *wp = a.out_words + (bitpos >> 5);
-                        atomicOr(wp, word << sh);
-                        if (sh && (word >> (32 - sh))) atomicOr(wp + 1, word >> (32 - sh));
-                    }
-                }
-                word = 0;
+    auto put_word = [&](int rel, int m) PBVD_INLINE_LAMBDA {
+        const int64_t bitpos = j.out_bit0 + rel;
+        if (j.out_mode == kOutDirect) {
+            const int64_t byte = bitpos >> 3;
+            if (m == 32 && byte + 4 <= j.out_bytes) {
+                *reinterpret_cast<uint32_t *>(j.out + byte) = word;
+            } else {
+                for (int bb = 0; bb < ((m + 7) >> 3); ++bb)
+                    if (byte + bb < j.out_bytes) j.out[byte + bb] = (uint8_t)(word >> (8 * bb));
             }
-        }
-        uint32_t dec;
-        if constexpr (NDW == 1) {
-            dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
-        } else if constexpr (NDW == 2) {
-            const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
-            dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
+        } else if (j.out_mode == kOutAtomic) {
+            const uint32_t sh = (uint32_t)(bitpos & 31);
+            uint32_t *wp = j.out_words + (bitpos >> 5);
+            atomicOr(wp, word << sh);
+            if (sh && (word >> (32 - sh))) atomicOr(wp + 1, word >> (32 - sh));
         } else {
-            // select dword idx >> 5 with a binary tree, most significant
-            // index bit first (v[w + half] differs from v[w] in that bit)
-            uint32_t v[NDW];
-#pragma unroll
-            for (int w = 0; w < NDW; ++w) v[w] = row[w];
-            constexpr int kTopBit = 4 + (NDW >= 8 ? 3 : NDW >= 4 ? 2 : 1);
-#pragma unroll
-            for (int half = NDW / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
-                const bool up = (idx >> bit) & 1u;
-#pragma unroll
-                for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
+            // the lane owns whole bytes: its first bit is byte aligned
+            uint8_t *ob = j.out + (bitpos >> 3);
+            if (m == 32 && (((uintptr_t)ob & 3u) == 0)) {
+                *reinterpret_cast<uint32_t *>(ob) = word;
+            } else {
+                for (int bb = 0; bb < ((m + 7) >> 3); ++bb) ob[bb] = (uint8_t)(word >> (8 * bb));
             }
-            dec = (v[0] >> (idx & 31u)) & 1u;
         }
-        idx = (idx & ~(1u << qpos)) | (dec << qpos);
+    };
+
+    // one traceback step at stage i with that stage's survivor row
+    auto step = [&](int i, const uint32_t (&row)[NDW], int sub) PBVD_INLINE_LAMBDA {
+        const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
+        bool live = true;
+        if constexpr (VARLEN) live = i < j.my_len && i >= j.my_store0;
+        if (live) {
+            const uint32_t x = (idx >> qpos) & 1u;
+            if (i < j.my_dec_end) {
+                word = (word << 1) | x;
+                const int rel = i - j.my_store0;
+                if ((rel & 31) == 0) {
+                    if (j.active) put_word(rel, n_dec - rel < 32 ? n_dec - rel : 32);
+                    word = 0;
+                }
+            }
+            uint32_t dec;
+            if constexpr (NDW == 1) {
+                dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
+            } else if constexpr (NDW == 2) {
+                const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
+                dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
+            } else {
+                // select dword idx >> 5 with a binary tree, most significant
+                // index bit first (v[w + half] differs from v[w] in that bit)
+                uint32_t v[NDW];
+#pragma unroll
+                for (int w = 0; w < NDW; ++w) v[w] = row[w];
+                constexpr int kTopBit = 4 + (NDW >= 8 ? 3 : NDW >= 4 ? 2 : 1);
+#pragma unroll
+                for (int half = NDW / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
+                    const bool up = (idx >> bit) & 1u;
+#pragma unroll
+                    for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
+                }
+                dec = (v[0] >> (idx & 31u)) & 1u;
+            }
+            idx = (idx & ~(1u << qpos)) | (dec << qpos);
+        }
         ph = ph == 0 ? V - 1 : ph - 1;
     };
 
-    // trace rows top..top-TBR+1; false once the first stored stage is passed
-    auto run_block = [&](const uint32_t (&blk)[TBR][NDW], int top) {
+    // trace rows top..top-TBR+1; false once the first traced stage is passed
+    auto run_block = [&](const uint32_t (&blk)[TBR][NDW], int top) PBVD_INLINE_LAMBDA {
         return static_for<0, TBR>([&](auto tc) PBVD_INLINE_LAMBDA {
             constexpr int t = decltype(tc)::value;
             const int row = top - t;
@@ -689,7 +667,7 @@ __global__ void __launch_bounds__(256)
                 constexpr int sub = S - 1 - decltype(sc)::value;
                 const int i = row * S + sub;
                 if (i >= len) return true;
-                if (i < i_store0) return false;
+                if (i < i_lo) return false;
                 step(i, blk[t], sub);
                 return true;
             });
@@ -707,6 +685,169 @@ __global__ void __launch_bounds__(256)
         if (!run_block(rb, top)) break;
         top -= TBR;
     }
+}
+
+// Register target for the 256-state trellis (waves per SIMD the compiler
+// must leave room for).  Two waves force scratch spills inside the stage
+// loop, which measured 2x slower than one wave with accumulator-register
+// spills.
+#ifndef PBVD_BIG_TRELLIS_WAVES_PER_EU
+#define PBVD_BIG_TRELLIS_WAVES_PER_EU 1
+#endif
+
+// ---------------------------------------------------------------------------
+// Stream kernel: the PBs of one stream (Sec. III-A, Fig. 2).  Interior PBs
+// (full geometry) go 64 to a wave; PBs at the stream ends get a wave each.
+// ---------------------------------------------------------------------------
+template <class C, class P, int KIND>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    decode_kernel(const KernelArgs a) {
+    using LY = Layout<C, P>;
+    constexpr int R = C::R, N = C::N;
+    constexpr int ND = (LY::U * R + 3) / 4 + 1;
+
+    const int lane = threadIdx.x & (kWave - 1);
+    // wave index made provably uniform so that all geometry stays scalar
+    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave_local >= a.n_waves) return;
+    const int64_t wave = a.wave_begin + wave_local;
+    const int64_t D = a.D, L = a.L;
+
+    // ---- block geometry (Sec. III-A with M = L, clipped to the stream) ----
+    int64_t b, f0w, f1w, d0w, d1w;   // wave-uniform PB geometry (interior: lane 0's)
+    bool active;
+    int64_t lane_stage_off;           // this lane's stage offset from f0w
+    int64_t far_lane;                 // the wave's last real lane
+    if (wave < a.n_int_waves) {
+        const int64_t bw = a.b_lo + wave * kWave;
+        b = bw + lane;
+        active = b < a.b_hi;
+        lane_stage_off = (active ? (int64_t)lane : (a.b_hi - 1 - bw)) * D;
+        if (!active) b = a.b_hi - 1;
+        far_lane = a.b_hi - 1 - bw < kWave - 1 ? a.b_hi - 1 - bw : kWave - 1;
+        d0w = bw * D;
+        f0w = d0w - L;
+        f1w = d0w + D + L;
+        d1w = d0w + D;
+    } else {
+        const int64_t e = wave - a.n_int_waves;
+        b = e < a.n_head ? a.pb_first + e : a.b_hi + (e - a.n_head);
+        active = lane == 0;
+        lane_stage_off = 0;
+        far_lane = 0;
+        d0w = b * D;
+        f0w = d0w - L < 0 ? 0 : d0w - L;
+        f1w = d0w + D + L > a.T ? a.T : d0w + D + L;
+        d1w = d0w + D > a.n ? a.n : d0w + D;
+    }
+    WaveJob j;
+    // stage counts fit in 32 bits (at most D + 2L), which keeps the loop
+    // control on the scalar unit
+    j.len = (int)(f1w - f0w);
+    j.store0_min = (int)(d0w - f0w);
+    j.my_len = j.len;
+    j.my_store0 = j.store0_min;
+    j.my_dec_end = (int)(d1w - f0w);
+    j.in = a.syms + (f0w + lane_stage_off) * R;
+    j.in_end = a.syms + a.T * R;
+    // wave-uniform: every wide fetch of every lane stays inside the input;
+    // only the last wave(s) of a stream take the byte-load path
+    j.fetch_safe = a.syms + (f0w + far_lane * D + (j.len - 1)) * R + 4 * ND <= j.in_end;
+    const int64_t safe_bytes = (int64_t)(j.in_end - (a.syms + (f0w + far_lane * D) * R)) - 4 * ND;
+    j.i_safe = safe_bytes < 0 ? -1 : (safe_bytes / R > j.len ? j.len : (int)(safe_bytes / R));
+    j.known = f0w + lane_stage_off == 0;  // an interior PB can start at 0 when L is a multiple of D
+    j.argmin = f1w == a.T && !a.terminated;
+    j.need_final = j.argmin || a.final_pm != nullptr;
+    j.active = active;
+    j.out_mode = a.direct_out ? kOutDirect : kOutAtomic;
+    j.out = a.out;
+    j.out_bytes = a.out_bytes;
+    j.out_words = a.out_words;
+    j.out_bit0 = (b - a.pb_first) * D;
+    j.pm_out = a.final_pm ? a.final_pm + (b - a.pb_first) * N : nullptr;
+
+    RowStore<LY::NDW> rows;
+    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
+                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
+    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
+    decode_body<C, P, KIND, false>(j, rows);
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernel: one wave per tile of up to 64 PBs of one code taken from any
+// frames (lengths may differ inside a tile).
+// ---------------------------------------------------------------------------
+struct LaneDesc {
+    int64_t sym;       // byte offset in syms of the PB's first forward stage
+    int64_t out_bit;   // bit offset in out of the PB's first decoded bit (byte aligned)
+    int32_t len;       // forward stages
+    int32_t store0;    // first traced stage
+    int32_t dec_end;   // end of the decoded range (stage index)
+    int32_t flags;     // kLaneKnown | kLaneArgmin | kLaneActive
+};
+struct TileHead {
+    int32_t len;        // longest lane
+    int32_t store0_min; // lowest first-traced stage
+    int32_t flags;      // kTileWide | kTileFinal
+    int32_t pad;
+};
+enum { kLaneKnown = 1, kLaneArgmin = 2, kLaneActive = 4 };
+enum { kTileWide = 1, kTileFinal = 2 };
+
+struct TileArgs {
+    const uint8_t *syms;
+    int64_t sym_bytes;
+    uint8_t *out;
+    const LaneDesc *lanes;   // [tiles][64]
+    const TileHead *heads;   // [tiles]
+    uint32_t *sp;
+    int64_t sp_wave_dwords;
+    int64_t tile_begin;
+    int64_t n_tiles;
+};
+
+template <class C, class P, int KIND>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    decode_tiles_kernel(const TileArgs a) {
+    using LY = Layout<C, P>;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave_local >= a.n_tiles) return;
+    const int64_t tile = a.tile_begin + wave_local;
+    const TileHead h = a.heads[tile];
+    const LaneDesc d = a.lanes[tile * kWave + lane];
+
+    WaveJob j;
+    j.len = __builtin_amdgcn_readfirstlane(h.len);
+    j.store0_min = __builtin_amdgcn_readfirstlane(h.store0_min);
+    const int tflags = __builtin_amdgcn_readfirstlane(h.flags);
+    j.fetch_safe = (tflags & kTileWide) != 0;
+    j.i_safe = j.fetch_safe ? j.len : -1;
+    j.need_final = (tflags & kTileFinal) != 0;
+    j.in_end = a.syms + a.sym_bytes;
+    j.in = a.syms + d.sym;
+    j.my_len = d.len;
+    j.my_store0 = d.store0;
+    j.my_dec_end = d.dec_end;
+    j.known = (d.flags & kLaneKnown) != 0;
+    j.argmin = (d.flags & kLaneArgmin) != 0;
+    j.active = (d.flags & kLaneActive) != 0;
+    j.out_mode = kOutBytes;
+    j.out = a.out;
+    j.out_bytes = 0;
+    j.out_words = nullptr;
+    j.out_bit0 = d.out_bit;
+    j.pm_out = nullptr;
+
+    RowStore<LY::NDW> rows;
+    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
+                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
+    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
+    decode_body<C, P, KIND, true>(j, rows);
 }
 
 }  // namespace pbvd

@@ -56,12 +56,29 @@ struct LaunchRequest {
 
 constexpr int kBlockThreads = 256;
 
+struct TileLaunchRequest {
+    TileArgs args;
+    int pm_bits;
+    int input_kind;
+    unsigned grid;
+    hipStream_t stream;
+};
+
 // Implemented by the translation unit compiled for code index IDX.
 template <int IDX>
 hipError_t launch_code(const LaunchRequest &req);
+template <int IDX>
+hipError_t launch_tiles(const TileLaunchRequest &req);
 
 // Survivor layout of a code: dwords per stored row and stages per row.
 __host__ __device__ constexpr int survivor_row_dwords(int K) { return (1 << (K - 2)) >= 16 ? (1 << (K - 2)) / 16 : 1; }
 __host__ __device__ constexpr int survivor_row_stages(int K) { return (1 << (K - 2)) >= 16 ? 1 : 16 / (1 << (K - 2)); }
+// Stages of one unrolled loop trip and dwords of one trip's symbol fetch
+// (the same numbers Layout<> derives on the device).
+__host__ __device__ constexpr int gcd_int(int a, int b) { return b == 0 ? a : gcd_int(b, a % b); }
+__host__ __device__ constexpr int trip_stages(int K) {
+    return (K - 1) / gcd_int(K - 1, survivor_row_stages(K)) * survivor_row_stages(K);
+}
+__host__ __device__ constexpr int trip_fetch_dwords(int K, int R) { return (trip_stages(K) * R + 3) / 4 + 1; }
 
 }  // namespace pbvd

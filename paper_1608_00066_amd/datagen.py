@@ -120,3 +120,29 @@ def make_stream(K: int, gens, n: int, ebn0_db: float | None, seed: int, kind: in
 def uncoded_ber(ebn0_db: float) -> float:
     """Bit error rate of uncoded BPSK, Q(sqrt(2 Eb/N0))."""
     return 0.5 * math.erfc(math.sqrt(10.0 ** (ebn0_db / 10.0)))
+
+
+def make_frames(codes, n_frames: int, len_lo: int, len_hi: int, seed: int, ebn0_lo: float = 1.0,
+                ebn0_hi: float = 5.0, gap: int = 0, lengths=None, code_ids=None):
+    """Many independent frames packed back to back: random code (uniform over
+    `codes`, each a dict with K, gens and optionally terminated / input_kind),
+    info length uniform in [len_lo, len_hi] (or `lengths`), Eb/N0 uniform in
+    [ebn0_lo, ebn0_hi].  Returns (frames, streams, syms, out_bytes) where
+    frames are (sym_offset, n_bits, out_offset, code) tuples and outputs are
+    byte aligned, `gap` bytes apart."""
+    rng = np.random.default_rng(seed)
+    frames, streams = [], []
+    sym_off = out_off = 0
+    for f in range(n_frames):
+        ci = int(code_ids[f]) if code_ids is not None else int(rng.integers(0, len(codes)))
+        c = codes[ci]
+        n = int(lengths[f]) if lengths is not None else int(rng.integers(len_lo, len_hi + 1))
+        ebn0 = float(rng.uniform(ebn0_lo, ebn0_hi))
+        st = make_stream(c["K"], c["gens"], n, ebn0, seed=seed * 1000003 + f,
+                         kind=c.get("input_kind", SOFT_I8), terminated=c.get("terminated", True))
+        frames.append((sym_off, n, out_off, ci))
+        streams.append(st)
+        sym_off += st["syms"].size
+        out_off += (n + 7) // 8 + gap
+    syms = np.concatenate([s["syms"] for s in streams]) if streams else np.zeros(0, np.uint8)
+    return frames, streams, syms, out_off

@@ -31,6 +31,12 @@ class pbvd_code(ctypes.Structure):
                 ("input_kind", ctypes.c_int32), ("pm_bits", ctypes.c_int32)]
 
 
+class pbvd_frame(ctypes.Structure):
+    _fields_ = [("sym_offset", ctypes.c_int64), ("n_bits", ctypes.c_int64),
+                ("out_offset", ctypes.c_int64), ("code", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class PbvdError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -51,6 +57,11 @@ SIGNATURES = {
     "pbvd_debug_survivors": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
     "pbvd_debug_branch_metrics": (_I32, [_P, _P, _I64, _P, _P]),
     "pbvd_destroy": (None, [_P]),
+    "pbvd_batch_create": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
+    "pbvd_batch_set_frames": (_I32, [_P, _P, _I64, _I64, _I64]),
+    "pbvd_batch_decode": (_I32, [_P, _P, _P, _P]),
+    "pbvd_batch_info": (_I32, [_P, _P, _P, _P, _P]),
+    "pbvd_batch_destroy": (None, [_P]),
     "pbvd_strerror": (ctypes.c_char_p, [_I32]),
     "pbvd_last_error": (ctypes.c_char_p, []),
 }
@@ -243,3 +254,75 @@ class Plan:
 def unpack_bits(packed: np.ndarray, n_bits: int) -> np.ndarray:
     """Packed output (bit i = bit i&7 of byte i>>3) to one uint8 per bit."""
     return np.unpackbits(np.asarray(packed, dtype=np.uint8), bitorder="little")[:n_bits]
+
+
+def _code_struct(K, gens, D, L, terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16):
+    c = pbvd_code()
+    c.K, c.R = K, len(gens)
+    for i, g in enumerate(gens[:4]):
+        c.gen[i] = int(g)
+    c.D, c.L, c.terminated, c.input_kind, c.pm_bits = D, L, int(terminated), input_kind, pm_bits
+    return c
+
+
+class Batch:
+    """pbvd_batch_*: many frames, several codes, one launch per code.
+
+    ``codes`` is a list of dicts with keys K, gens, D, L and optionally
+    terminated, input_kind, pm_bits."""
+
+    def __init__(self, codes):
+        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16)
+        self.codes = [{**defaults, **c} for c in codes]
+        arr = (pbvd_code * len(codes))(*[_code_struct(**c) for c in self.codes])
+        h = ctypes.c_void_p()
+        _check(lib().pbvd_batch_create(ctypes.cast(arr, ctypes.c_void_p), len(codes),
+                                       ctypes.byref(h)), "pbvd_batch_create")
+        self.handle = h.value
+        self.n_frames = 0
+
+    def close(self):
+        if self.handle:
+            lib().pbvd_batch_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_frames(self, frames, sym_bytes: int, out_bytes: int):
+        """frames: iterable of (sym_offset, n_bits, out_offset, code)."""
+        frames = list(frames)
+        arr = (pbvd_frame * max(len(frames), 1))()
+        for i, (so, nb, oo, code) in enumerate(frames):
+            arr[i].sym_offset, arr[i].n_bits, arr[i].out_offset = int(so), int(nb), int(oo)
+            arr[i].code, arr[i].reserved = int(code), 0
+        _check(lib().pbvd_batch_set_frames(ctypes.c_void_p(self.handle),
+                                           ctypes.cast(arr, ctypes.c_void_p), len(frames),
+                                           int(sym_bytes), int(out_bytes)),
+               "pbvd_batch_set_frames")
+        self.n_frames = len(frames)
+
+    def decode(self, syms, out, stream=None):
+        import torch
+        st = lib().pbvd_batch_decode(ctypes.c_void_p(self.handle),
+                                     _dev_ptr(syms, "syms", 0, (torch.uint8, torch.int8)),
+                                     _dev_ptr(out, "out", 0, (torch.uint8,)),
+                                     _stream_handle(stream))
+        _check(st, "pbvd_batch_decode")
+        return out
+
+    def info(self):
+        v = [ctypes.c_int64() for _ in range(4)]
+        _check(lib().pbvd_batch_info(ctypes.c_void_p(self.handle), *[ctypes.byref(x) for x in v]),
+               "pbvd_batch_info")
+        return dict(zip(("tiles", "blocks", "forward_stages", "workspace_bytes"),
+                        (x.value for x in v)))

@@ -106,3 +106,18 @@ def test_block_geometry_matches_oracle(pbvd, K, gens, D, L, n, term):
         assert np.array_equal(sub, want[nb // 2:])
     finally:
         pbvd.pbvd_destroy(h)
+
+
+def test_batch_rejects_bad_frames(pbvd):
+    codes = [dict(K=7, gens=(0o171, 0o133), D=512, L=42)]
+    with pbvd.Batch(codes) as b:
+        for frames, sb, ob in [([(0, 100, 0, 1)], 1000, 100),        # bad code index
+                               ([(900, 100, 0, 0)], 1000, 100),      # symbols past the input
+                               ([(0, 100, 90, 0)], 1000, 100),       # output past the buffer
+                               ([(0, 100, 0, 0), (0, 100, 5, 0)], 1000, 100),  # overlap
+                               ([(0, 0, 0, 0)], 1000, 100)]:         # empty frame
+            with pytest.raises(pbvd.PbvdError) as ei:
+                b.set_frames(frames, sb, ob)
+            assert ei.value.status == pbvd.PBVD_EINVAL
+    with pytest.raises(pbvd.PbvdError):
+        pbvd.Batch([dict(K=7, gens=(0o171, 0o133), D=100, L=42)])  # D % 8 != 0

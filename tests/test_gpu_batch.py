@@ -1,0 +1,125 @@
+"""Batched decoding (many frames, several codes, one launch per code) against
+the CPU oracle frame by frame, against per-frame stream decoding, and under
+HIP-graph capture and replay."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00066_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def pbvd():
+    from paper_1608_00066_amd import pbvd as mod
+    mod.lib()
+    return mod
+
+
+def make_batch(codes, n_frames, lo, hi, seed, gap=1):
+    """Frames with random lengths/codes/Eb-N0 packed back to back; output
+    ranges separated by `gap` bytes that must stay untouched."""
+    return datagen.make_frames(codes, n_frames, lo, hi, seed, gap=gap)
+
+
+def check_batch(torch, pbvd, codes, n_frames, lo, hi, seed):
+    frames, streams, syms, out_bytes = make_batch(codes, n_frames, lo, hi, seed)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.full((out_bytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        info = b.info()
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    covered = np.zeros(out_bytes, dtype=bool)
+    for (so, n, oo, ci), st in zip(frames, streams):
+        c = {**dict(terminated=True, input_kind=0), **codes[ci]}
+        nbytes = (n + 7) // 8
+        got = np.unpackbits(host[oo:oo + nbytes], bitorder="little")[:n]
+        ref = oracle.decode(c["K"], c["gens"], c["D"], c["L"], st["syms"], n,
+                            terminated=c["terminated"], input_kind=c["input_kind"])
+        bad = np.flatnonzero(got != ref["bits"])
+        assert bad.size == 0, "frame at %d (n=%d code %d): bits differ at %s" % (so, n, ci, bad[:8])
+        # pad bits of the last byte are zero
+        assert np.all(np.unpackbits(host[oo:oo + nbytes], bitorder="little")[n:] == 0)
+        covered[oo:oo + nbytes] = True
+    assert np.all(host[~covered] == 0xA5), "bytes outside the frames were written"
+    return frames, streams, syms, out_bytes, info
+
+
+def test_batch_mixed_k7_codes(torch, pbvd):
+    codes = [dict(K=7, gens=(0o171, 0o133), D=512, L=42),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=512, L=42)]
+    log("batch: 300 frames K=7 r1/2 + r1/3, lengths 40..3000")
+    _, _, _, _, info = check_batch(torch, pbvd, codes, 300, 40, 3000, seed=7)
+    assert info["tiles"] >= 2 and info["blocks"] >= 300
+
+
+def test_batch_matches_stream_decoder(torch, pbvd):
+    """Every frame of a batch equals decoding that frame alone."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=256, L=42)]
+    frames, streams, syms, out_bytes, _ = check_batch(torch, pbvd, codes, 64, 40, 5000, seed=11)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        b.decode(d_syms, out)
+    with pbvd.Plan(7, (0o171, 0o133), 256, 42) as plan:
+        for (so, n, oo, ci), st in zip(frames[:16], streams[:16]):
+            alone = plan.decode(torch.from_numpy(st["syms"]).cuda(), n)
+            torch.cuda.synchronize()
+            assert np.array_equal(alone.cpu().numpy(), out[oo:oo + (n + 7) // 8].cpu().numpy())
+
+
+def test_batch_unterminated_hard_int32_and_small_trellis(torch, pbvd):
+    codes = [dict(K=3, gens=(0o7, 0o5), D=64, L=16, terminated=False, input_kind=1, pm_bits=32),
+             dict(K=5, gens=(0o23, 0o35), D=256, L=30),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=96, L=54, terminated=False)]
+    log("batch: K=3 hard/int32/unterminated + K=5 + K=9 unterminated, lengths 1..700")
+    check_batch(torch, pbvd, codes, 120, 1, 700, seed=21)
+
+
+def test_batch_graph_capture_replays(torch, pbvd):
+    """The decode call only launches kernels: capture it in a HIP graph and
+    replay it several times with eager work in between."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=512, L=42),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=512, L=42)]
+    frames, streams, syms, out_bytes = make_batch(codes, 100, 40, 2000, seed=31, gap=0)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+        eager = out.clone()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                b.decode(d_syms, out)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager)
+        del g
