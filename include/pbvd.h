@@ -66,7 +66,8 @@ typedef enum {
     PBVD_EINVAL = -1,   /* invalid argument */
     PBVD_ENOTSUP = -2,  /* valid code, but no kernel compiled for it */
     PBVD_ENOMEM = -3,   /* device workspace allocation failed */
-    PBVD_EHIP = -4      /* HIP runtime error (detail in pbvd_last_error) */
+    PBVD_EHIP = -4,     /* HIP runtime error (detail in pbvd_last_error) */
+    PBVD_EAGAIN = -5    /* server: request not finished yet, or queue full */
 } pbvd_status;
 
 enum {
@@ -197,6 +198,69 @@ pbvd_status pbvd_batch_info(const pbvd_batch *b, int64_t *n_tiles, int64_t *n_bl
 
 /* Free the batch and its device memory (synchronizes the device). */
 void pbvd_batch_destroy(pbvd_batch *b);
+
+/* ---- Request server: continuous batching of decode requests -------------
+ *
+ * A server decodes independent requests (one frame each, host memory in and
+ * out) as they arrive.  A worker thread keeps up to max_inflight batches on
+ * the device at once, each in its own part of a fixed device-memory budget
+ * with its own streams: whenever a part is free and requests wait, it admits
+ * the waiting requests that fit (first come, first served), copies their
+ * symbols and work list to the device in one transfer, runs the batched
+ * kernels of pbvd_batch_decode and copies the bits back.  Requests arriving
+ * while batches run are admitted as parts free up, so their work overlaps on
+ * the device.  Each request's bits equal pbvd_decode of its frame alone with
+ * the same code parameters, whatever it was batched with. */
+
+typedef struct pbvd_server pbvd_server;
+
+typedef struct {
+    int64_t device_bytes;     /* device memory of all batches in flight: inputs,
+                                 outputs, work lists and survivor rows; split
+                                 evenly between max_inflight batches; at least
+                                 1 MiB per batch */
+    int32_t max_inflight;     /* batches on the device at once, 1..8 */
+    int32_t max_batch_frames; /* requests per batch, >= 1 */
+    int64_t max_queued;       /* requests waiting for admission, >= 1; beyond it
+                                 pbvd_server_submit returns PBVD_EAGAIN */
+} pbvd_server_config;
+
+typedef struct {
+    int64_t submit_ns;    /* steady-clock time of pbvd_server_submit */
+    int64_t start_ns;     /* when the batch carrying it was launched */
+    int64_t done_ns;      /* when its bits were in the caller's buffer */
+    int32_t batch_frames; /* requests in that batch */
+    int32_t status;       /* PBVD_OK, or the failure of its batch */
+} pbvd_request_info;
+
+/* Create a server for n_codes (1..16) code/block parameter sets (each valid
+ * for pbvd_batch_create) on the current device.  Allocates the device budget
+ * and pinned staging buffers and starts the worker thread. */
+pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pbvd_server_config *cfg,
+                               pbvd_server **out);
+
+/* Queue one request: frame of n_bits information bits of code index `code`,
+ * host symbols (layout of pbvd_decode; copied before the call returns) and a
+ * host output buffer of ceil(n_bits/8) bytes that must stay valid until the
+ * request is waited for.  *ticket identifies it.  PBVD_EINVAL if the request
+ * alone exceeds one batch's part of the budget, PBVD_EAGAIN if the queue is
+ * full.  Thread-safe. */
+pbvd_status pbvd_server_submit(pbvd_server *s, int32_t code, const void *syms, int64_t n_bits,
+                               uint8_t *out_bits, int64_t *ticket);
+
+/* Wait for a request (timeout_us < 0: without limit).  On return with
+ * PBVD_OK its bits are in the output buffer; info (may be NULL) receives its
+ * timing.  The ticket is released by a return other than PBVD_EAGAIN
+ * (timeout).  Thread-safe. */
+pbvd_status pbvd_server_wait(pbvd_server *s, int64_t ticket, int64_t timeout_us, pbvd_request_info *info);
+
+/* Batches launched, requests finished and the largest number of batches that
+ * were in flight at once; any pointer may be NULL. */
+pbvd_status pbvd_server_counters(pbvd_server *s, int64_t *batches, int64_t *requests_done,
+                                 int64_t *peak_inflight);
+
+/* Finish every queued request, stop the worker and free the server. */
+void pbvd_server_destroy(pbvd_server *s);
 
 /* Static description of a status code. */
 const char *pbvd_strerror(pbvd_status s);

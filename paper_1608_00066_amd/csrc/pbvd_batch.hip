@@ -1,0 +1,365 @@
+// Batched decoding (pbvd_batch_* of include/pbvd.h): the work-list builder
+// that packs the parallel blocks of many frames into waves, and the batch
+// object that uploads it once and launches one kernel per code, the codes
+// on forked streams so their launches overlap on the device.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "pbvd.h"
+#include "pbvd_host.hpp"
+#include "pbvd_registry.hpp"
+
+namespace pbvd_host {
+
+pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out) {
+    if (!codes) return fail(PBVD_EINVAL, "codes must not be NULL");
+    if (n < 1 || n > kMaxCodes) return fail(PBVD_EINVAL, "n_codes must be in [1, %d]", kMaxCodes);
+    CodeSet cs;
+    for (int i = 0; i < n; ++i) {
+        int idx = -1;
+        pbvd_status st = check_code(codes[i], &idx);
+        if (st != PBVD_OK) return st;
+        if (codes[i].D % 8 != 0)
+            return fail(PBVD_EINVAL, "code %d: batched decoding needs D %% 8 == 0 (got %d)", i, codes[i].D);
+        cs.codes[i] = codes[i];
+        for (int r = codes[i].R; r < 4; ++r) cs.codes[i].gen[r] = 0;
+        cs.idx[i] = idx;
+    }
+    cs.n = n;
+    *out = cs;
+    return PBVD_OK;
+}
+
+namespace {
+
+// One parallel block of one frame (Sec. III-A), in the batch's coordinates.
+struct PbRec {
+    int64_t sym, out_bit;
+    int32_t len, store0, dec_end, flags;
+};
+
+}  // namespace
+
+pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl) {
+    std::vector<std::vector<PbRec>> per_code(cs.n);
+    std::vector<std::pair<int64_t, int64_t>> outs;
+    outs.reserve((size_t)n_frames);
+    wl->n_blocks = 0;
+    wl->n_stages = 0;
+    for (int64_t f = 0; f < n_frames; ++f) {
+        const pbvd_frame &fr = frames[f];
+        if (fr.code < 0 || fr.code >= cs.n || fr.reserved != 0)
+            return fail(PBVD_EINVAL, "frame %lld: bad code index %d", (long long)f, fr.code);
+        const pbvd_code &c = cs.codes[fr.code];
+        if (fr.n_bits < 1) return fail(PBVD_EINVAL, "frame %lld: n_bits must be >= 1", (long long)f);
+        const int64_t T = fr.n_bits + (c.terminated ? c.K - 1 : 0);
+        if (fr.sym_offset < 0 || fr.sym_offset > sym_bytes - T * c.R)
+            return fail(PBVD_EINVAL, "frame %lld: symbols outside the %lld-byte input", (long long)f,
+                        (long long)sym_bytes);
+        const int64_t nbytes = ceil_div(fr.n_bits, 8);
+        if (fr.out_offset < 0 || fr.out_offset > out_bytes - nbytes)
+            return fail(PBVD_EINVAL, "frame %lld: output outside the %lld-byte buffer", (long long)f,
+                        (long long)out_bytes);
+        outs.emplace_back(fr.out_offset, fr.out_offset + nbytes);
+        const int64_t D = c.D, L = c.L;
+        const int64_t nb = ceil_div(fr.n_bits, D);
+        for (int64_t pb = 0; pb < nb; ++pb) {
+            const int64_t d0 = pb * D;
+            const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
+            const int64_t f1 = d0 + D + L > T ? T : d0 + D + L;
+            const int64_t d1 = d0 + D > fr.n_bits ? fr.n_bits : d0 + D;
+            PbRec r;
+            r.sym = fr.sym_offset + f0 * c.R;
+            r.out_bit = fr.out_offset * 8 + d0;
+            r.len = (int32_t)(f1 - f0);
+            r.store0 = (int32_t)(d0 - f0);
+            r.dec_end = (int32_t)(d1 - f0);
+            r.flags = pbvd::kLaneActive | (f0 == 0 ? pbvd::kLaneKnown : 0) |
+                      (f1 == T && !c.terminated ? pbvd::kLaneArgmin : 0);
+            per_code[fr.code].push_back(r);
+            wl->n_stages += r.len;
+        }
+        wl->n_blocks += nb;
+    }
+    std::sort(outs.begin(), outs.end());
+    for (size_t i = 1; i < outs.size(); ++i)
+        if (outs[i].first < outs[i - 1].second)
+            return fail(PBVD_EINVAL, "frame output ranges overlap at byte %lld", (long long)outs[i].first);
+
+    wl->lanes.clear();
+    wl->heads.clear();
+    for (int ci = 0; ci < cs.n; ++ci) {
+        const pbvd_code &c = cs.codes[ci];
+        const int64_t U = pbvd::trip_stages(c.K);
+        const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
+        std::vector<PbRec> &v = per_code[ci];
+        // longest first (load balance); PBs that start their traceback from
+        // the best state must share a tile with PBs of the same length only,
+        // so that all of a tile's final metrics are taken at one stage
+        std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) {
+            const bool ax = x.flags & pbvd::kLaneArgmin, ay = y.flags & pbvd::kLaneArgmin;
+            if (ax != ay) return ax < ay;
+            return x.len > y.len;
+        });
+        wl->groups[ci].tile_begin = (int64_t)wl->heads.size();
+        size_t i = 0;
+        while (i < v.size()) {
+            size_t e = std::min(v.size(), i + (size_t)pbvd::kWave);
+            if (v[i].flags & pbvd::kLaneArgmin) {
+                size_t k = i + 1;
+                while (k < e && (v[k].flags & pbvd::kLaneArgmin) && v[k].len == v[i].len) ++k;
+                e = k;
+            } else {
+                size_t k = i + 1;
+                while (k < e && !(v[k].flags & pbvd::kLaneArgmin)) ++k;
+                e = k;
+            }
+            pbvd::TileHead h{};
+            h.len = 0;
+            h.store0_min = 0x7fffffff;
+            bool wide = true, final_needed = false;
+            for (size_t k = i; k < i + pbvd::kWave; ++k) {
+                // lanes past the tile's PBs repeat its first PB, inactive
+                const PbRec &r = v[k < e ? k : i];
+                pbvd::LaneDesc d;
+                d.sym = r.sym;
+                d.out_bit = r.out_bit;
+                d.len = r.len;
+                d.store0 = r.store0;
+                d.dec_end = r.dec_end;
+                d.flags = k < e ? r.flags : (r.flags & ~pbvd::kLaneActive);
+                wl->lanes.push_back(d);
+                if (r.len > h.len) h.len = r.len;
+                if (r.store0 < h.store0_min) h.store0_min = r.store0;
+                const int64_t last_trip = ((r.len - 1) / U) * U;
+                if (r.sym + last_trip * c.R + 4 * ND > sym_bytes) wide = false;
+                if (r.flags & pbvd::kLaneArgmin) final_needed = true;
+            }
+            h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0);
+            wl->heads.push_back(h);
+            i = e;
+        }
+        wl->groups[ci].n_tiles = (int64_t)wl->heads.size() - wl->groups[ci].tile_begin;
+        wl->groups[ci].sp_wave_dwords = slot_dwords(c);
+    }
+    return PBVD_OK;
+}
+
+pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const uint8_t *d_syms,
+                         int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
+                         const pbvd::TileHead *d_heads, uint32_t *sp, int64_t per_launch,
+                         hipStream_t stream) {
+    const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
+    for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
+        pbvd::TileLaunchRequest req{};
+        pbvd::TileArgs &a = req.args;
+        a.syms = d_syms;
+        a.sym_bytes = sym_bytes;
+        a.out = d_out;
+        a.lanes = d_lanes;
+        a.heads = d_heads;
+        a.sp = sp;
+        a.sp_wave_dwords = g.sp_wave_dwords;
+        a.tile_begin = g.tile_begin + t0;
+        a.n_tiles = std::min(per_launch, g.n_tiles - t0);
+        req.pm_bits = cs.codes[ci].pm_bits;
+        req.input_kind = cs.codes[ci].input_kind;
+        req.grid = (unsigned)ceil_div(a.n_tiles, waves_per_block);
+        req.stream = stream;
+        hipError_t e = launch_tiles(cs.idx[ci], req);
+        if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
+    }
+    return PBVD_OK;
+}
+
+}  // namespace pbvd_host
+
+using namespace pbvd_host;
+
+struct pbvd_batch {
+    CodeSet cs;
+    int device = 0;
+    TileGroup groups[kMaxCodes];
+    int64_t per_launch[kMaxCodes];  // waves per launch of each code
+    int64_t sp_off[kMaxCodes];      // dword offset of each code's survivor area
+    int64_t n_tiles = 0, n_blocks = 0, n_stages = 0;
+    int64_t sym_bytes = 0, out_bytes = 0;
+    pbvd::LaneDesc *d_lanes = nullptr;
+    pbvd::TileHead *d_heads = nullptr;
+    size_t lanes_bytes = 0, heads_bytes = 0;
+    uint32_t *sp = nullptr;
+    size_t sp_bytes = 0;
+    // codes after the first run on these streams, forked from and joined to
+    // the caller's stream with events
+    hipStream_t aux[kMaxCodes] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kMaxCodes] = {};
+};
+
+namespace {
+
+void release(pbvd_batch *b) {
+    DeviceGuard dg(b->device);
+    if (b->sp || b->d_lanes || b->d_heads) (void)hipDeviceSynchronize();
+    if (b->sp) (void)hipFree(b->sp);
+    if (b->d_lanes) (void)hipFree(b->d_lanes);
+    if (b->d_heads) (void)hipFree(b->d_heads);
+    for (int i = 0; i < kMaxCodes; ++i) {
+        if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
+        if (b->join[i]) (void)hipEventDestroy(b->join[i]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+}
+
+}  // namespace
+
+extern "C" {
+
+pbvd_status pbvd_batch_create(const pbvd_code *codes, int32_t n_codes, pbvd_batch **out) {
+    g_last_error[0] = 0;
+    if (!codes || !out) return fail(PBVD_EINVAL, "codes and out must not be NULL");
+    CodeSet cs;
+    const pbvd_status st = make_code_set(codes, n_codes, &cs);
+    if (st != PBVD_OK) return st;
+    pbvd_batch *b = new (std::nothrow) pbvd_batch();
+    if (!b) return fail(PBVD_ENOMEM, "host allocation failed");
+    b->cs = cs;
+    if (hipGetDevice(&b->device) != hipSuccess) b->device = 0;
+    (void)hipGetLastError();
+    *out = b;
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64_t n_frames,
+                                  int64_t sym_bytes, int64_t out_bytes) {
+    g_last_error[0] = 0;
+    if (!b) return fail(PBVD_EINVAL, "batch is NULL");
+    if (n_frames < 0 || (n_frames > 0 && !frames)) return fail(PBVD_EINVAL, "bad frame array");
+    if (sym_bytes < 0 || out_bytes < 0) return fail(PBVD_EINVAL, "negative buffer size");
+    WorkList wl;
+    pbvd_status st;
+    try {
+        st = build_work_list(b->cs, frames, n_frames, sym_bytes, out_bytes, &wl);
+    } catch (...) {
+        st = fail(PBVD_ENOMEM, "host allocation failed while building the work list");
+    }
+    if (st != PBVD_OK) return st;
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", b->device);
+    {
+        // streams and events of the fork, made once, outside any capture
+        hipError_t e = hipSuccess;
+        if (!b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int i = 1; i < b->cs.n && e == hipSuccess; ++i) {
+            if (!b->aux[i]) e = hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking);
+            if (e == hipSuccess && !b->join[i]) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) return fail_hip(e, "stream/event creation");
+    }
+    // survivor areas: each code gets its own (codes run concurrently); all of
+    // a code's tiles in one launch when the budget allows, else the budget is
+    // split evenly between the codes and their launches reuse their area
+    const int64_t budget = workspace_budget_bytes();
+    int64_t full = 0;
+    for (int ci = 0; ci < b->cs.n; ++ci) full += wl.groups[ci].n_tiles * wl.groups[ci].sp_wave_dwords * 4;
+    int64_t per_launch[kMaxCodes], sp_off[kMaxCodes], total = 0;
+    for (int ci = 0; ci < b->cs.n; ++ci) {
+        const TileGroup &g = wl.groups[ci];
+        int64_t n = g.n_tiles;
+        if (full > budget) n = std::min(n, std::max<int64_t>(1, budget / b->cs.n / (g.sp_wave_dwords * 4)));
+        per_launch[ci] = std::max<int64_t>(1, n);
+        sp_off[ci] = total;
+        total += g.n_tiles > 0 ? per_launch[ci] * g.sp_wave_dwords : 0;
+    }
+    st = ensure_buffer(&b->sp, &b->sp_bytes, (size_t)std::max<int64_t>(total, 64) * 4, "survivors");
+    if (st != PBVD_OK) return st;
+    const size_t lb = std::max<size_t>(wl.lanes.size(), 1) * sizeof(pbvd::LaneDesc);
+    const size_t hb = std::max<size_t>(wl.heads.size(), 1) * sizeof(pbvd::TileHead);
+    st = ensure_buffer(reinterpret_cast<uint32_t **>(&b->d_lanes), &b->lanes_bytes, lb, "work list");
+    if (st != PBVD_OK) return st;
+    st = ensure_buffer(reinterpret_cast<uint32_t **>(&b->d_heads), &b->heads_bytes, hb, "work list");
+    if (st != PBVD_OK) return st;
+    if (!wl.lanes.empty()) {
+        hipError_t e = hipMemcpy(b->d_lanes, wl.lanes.data(), wl.lanes.size() * sizeof(pbvd::LaneDesc),
+                                 hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_heads, wl.heads.data(), wl.heads.size() * sizeof(pbvd::TileHead),
+                          hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_hip(e, "work-list upload");
+    }
+    for (int ci = 0; ci < b->cs.n; ++ci) {
+        b->groups[ci] = wl.groups[ci];
+        b->per_launch[ci] = per_launch[ci];
+        b->sp_off[ci] = sp_off[ci];
+    }
+    b->n_tiles = (int64_t)wl.heads.size();
+    b->n_blocks = wl.n_blocks;
+    b->n_stages = wl.n_stages;
+    b->sym_bytes = sym_bytes;
+    b->out_bytes = out_bytes;
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out, void *hip_stream) {
+    g_last_error[0] = 0;
+    if (!b) return fail(PBVD_EINVAL, "batch is NULL");
+    if (b->n_tiles == 0) return PBVD_OK;
+    if (!d_syms || !d_out) return fail(PBVD_EINVAL, "NULL buffer");
+    if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", b->device);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int active[kMaxCodes], n_active = 0;
+    for (int ci = 0; ci < b->cs.n; ++ci)
+        if (b->groups[ci].n_tiles > 0) active[n_active++] = ci;
+    if (n_active > 1) {
+        hipError_t e = hipEventRecord(b->fork, s);
+        if (e != hipSuccess) return fail_hip(e, "fork event");
+    }
+    // codes after the first on their own streams, the first on the caller's,
+    // then the caller's stream waits for all of them
+    for (int k = 1; k < n_active; ++k) {
+        const int ci = active[k];
+        hipError_t e = hipStreamWaitEvent(b->aux[ci], b->fork, 0);
+        if (e != hipSuccess) return fail_hip(e, "fork wait");
+        pbvd_status st = launch_group(b->cs, ci, b->groups[ci], (const uint8_t *)d_syms, b->sym_bytes,
+                                      d_out, b->d_lanes, b->d_heads, b->sp + b->sp_off[ci],
+                                      b->per_launch[ci], b->aux[ci]);
+        if (st != PBVD_OK) return st;
+        e = hipEventRecord(b->join[ci], b->aux[ci]);
+        if (e != hipSuccess) return fail_hip(e, "join event");
+    }
+    const int c0 = active[0];
+    pbvd_status st = launch_group(b->cs, c0, b->groups[c0], (const uint8_t *)d_syms, b->sym_bytes, d_out,
+                                  b->d_lanes, b->d_heads, b->sp + b->sp_off[c0], b->per_launch[c0], s);
+    if (st != PBVD_OK) return st;
+    for (int k = 1; k < n_active; ++k) {
+        hipError_t e = hipStreamWaitEvent(s, b->join[active[k]], 0);
+        if (e != hipSuccess) return fail_hip(e, "join wait");
+    }
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_batch_info(const pbvd_batch *b, int64_t *n_tiles, int64_t *n_blocks,
+                            int64_t *n_forward_stages, int64_t *workspace_bytes) {
+    if (!b) return fail(PBVD_EINVAL, "batch is NULL");
+    if (n_tiles) *n_tiles = b->n_tiles;
+    if (n_blocks) *n_blocks = b->n_blocks;
+    if (n_forward_stages) *n_forward_stages = b->n_stages;
+    if (workspace_bytes) *workspace_bytes = (int64_t)(b->sp_bytes + b->lanes_bytes + b->heads_bytes);
+    return PBVD_OK;
+}
+
+void pbvd_batch_destroy(pbvd_batch *b) {
+    if (!b) return;
+    release(b);
+    delete b;
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+// Host-side pieces shared by the C ABI units (single-stream plans, batches,
+// the request server): error reporting, code validation, device buffers and
+// the work-list builder of batched decoding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "pbvd.h"
+#include "pbvd_registry.hpp"
+
+namespace pbvd_host {
+
+// Detail of the last failure of the calling thread (pbvd_last_error).
+extern thread_local char g_last_error[512];
+
+pbvd_status fail(pbvd_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+pbvd_status fail_hip(hipError_t e, const char *what);
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// PBVD_FAULT_INJECT=<site> makes the named host step fail (error-path tests).
+bool fault_injected(const char *site);
+
+// Makes a device current for the lifetime of the guard.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev);
+    ~DeviceGuard();
+};
+
+// Grows a device buffer to at least `need` bytes (contents are not kept).
+pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char *what);
+
+// Validates a code/block parameter set; *idx_out receives its registry index.
+pbvd_status check_code(const pbvd_code &c, int *idx_out);
+
+// Survivor dwords of one wave slot of a code (all D + 2L forward rows).
+int64_t slot_dwords(const pbvd_code &c);
+
+// Survivor workspace limit of one plan or batch (PBVD_WORKSPACE_MB, default 8 GiB).
+int64_t workspace_budget_bytes();
+
+// Launches the tile kernel of registry entry code_idx.
+hipError_t launch_tiles(int code_idx, const pbvd::TileLaunchRequest &req);
+
+// ---- batched decoding work list --------------------------------------------
+
+constexpr int kMaxCodes = 16;
+
+struct CodeSet {
+    int n = 0;
+    pbvd_code codes[kMaxCodes];
+    int idx[kMaxCodes];
+};
+
+// Validates n codes for batched use (D % 8 == 0) into *out.
+pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out);
+
+struct TileGroup {
+    int64_t tile_begin = 0, n_tiles = 0;
+    int64_t sp_wave_dwords = 0;
+};
+
+// Tiles (waves of 64 PBs) of a set of frames, grouped by code.
+struct WorkList {
+    std::vector<pbvd::LaneDesc> lanes;   // 64 per tile
+    std::vector<pbvd::TileHead> heads;   // one per tile
+    TileGroup groups[kMaxCodes];
+    int64_t n_blocks = 0, n_stages = 0;
+};
+
+// Builds the work list of `frames` (validated against the buffer sizes).
+pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl);
+
+// Launches the tile kernels of one code group: tiles [g.tile_begin, + g.n_tiles)
+// of the uploaded work list, at most `per_launch` waves per launch sharing
+// the survivor area `sp` one launch after another.
+pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const uint8_t *d_syms,
+                         int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
+                         const pbvd::TileHead *d_heads, uint32_t *sp, int64_t per_launch,
+                         hipStream_t stream);
+
+}  // namespace pbvd_host

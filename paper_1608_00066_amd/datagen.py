@@ -146,3 +146,34 @@ def make_frames(codes, n_frames: int, len_lo: int, len_hi: int, seed: int, ebn0_
         out_off += (n + 7) // 8 + gap
     syms = np.concatenate([s["syms"] for s in streams]) if streams else np.zeros(0, np.uint8)
     return frames, streams, syms, out_off
+
+
+def lognormal_lengths(rng: np.random.Generator, n: int, median: float = 1500.0, sigma: float = 1.0,
+                      lo: int = 40, hi: int = 65536) -> np.ndarray:
+    """Request lengths: log-normal with the given median and sigma (of the
+    log), rounded and clipped to [lo, hi]."""
+    x = rng.lognormal(mean=math.log(median), sigma=sigma, size=n)
+    return np.clip(np.rint(x), lo, hi).astype(np.int64)
+
+
+def poisson_arrivals(rng: np.random.Generator, n: int, rate: float) -> np.ndarray:
+    """Arrival times in seconds of a Poisson process of the given rate."""
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+def make_requests(codes, n: int, seed: int, median: float = 1500.0, sigma: float = 1.0,
+                  lo: int = 40, hi: int = 65536, ebn0_lo: float = 1.0, ebn0_hi: float = 5.0):
+    """Serving requests: code uniform over `codes`, log-normal length,
+    Eb/N0 uniform in [ebn0_lo, ebn0_hi].  Returns a list of
+    (code index, stream dict)."""
+    rng = np.random.default_rng(seed)
+    lengths = lognormal_lengths(rng, n, median, sigma, lo, hi)
+    out = []
+    for i in range(n):
+        ci = int(rng.integers(0, len(codes)))
+        c = codes[ci]
+        ebn0 = float(rng.uniform(ebn0_lo, ebn0_hi))
+        st = make_stream(c["K"], c["gens"], int(lengths[i]), ebn0, seed=seed * 1000003 + i,
+                         kind=c.get("input_kind", SOFT_I8), terminated=c.get("terminated", True))
+        out.append((ci, st))
+    return out

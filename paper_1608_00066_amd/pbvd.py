@@ -21,6 +21,7 @@ PBVD_EINVAL = -1
 PBVD_ENOTSUP = -2
 PBVD_ENOMEM = -3
 PBVD_EHIP = -4
+PBVD_EAGAIN = -5
 PBVD_SOFT_I8 = 0
 PBVD_HARD_U8 = 1
 
@@ -35,6 +36,17 @@ class pbvd_frame(ctypes.Structure):
     _fields_ = [("sym_offset", ctypes.c_int64), ("n_bits", ctypes.c_int64),
                 ("out_offset", ctypes.c_int64), ("code", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
+
+
+class pbvd_server_config(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_int64), ("max_inflight", ctypes.c_int32),
+                ("max_batch_frames", ctypes.c_int32), ("max_queued", ctypes.c_int64)]
+
+
+class pbvd_request_info(ctypes.Structure):
+    _fields_ = [("submit_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64), ("batch_frames", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
 
 
 class PbvdError(RuntimeError):
@@ -62,6 +74,11 @@ SIGNATURES = {
     "pbvd_batch_decode": (_I32, [_P, _P, _P, _P]),
     "pbvd_batch_info": (_I32, [_P, _P, _P, _P, _P]),
     "pbvd_batch_destroy": (None, [_P]),
+    "pbvd_server_create": (_I32, [_P, _I32, _P, ctypes.POINTER(_P)]),
+    "pbvd_server_submit": (_I32, [_P, _I32, _P, _I64, _P, ctypes.POINTER(_I64)]),
+    "pbvd_server_wait": (_I32, [_P, _I64, _I64, _P]),
+    "pbvd_server_counters": (_I32, [_P, _P, _P, _P]),
+    "pbvd_server_destroy": (None, [_P]),
     "pbvd_strerror": (ctypes.c_char_p, [_I32]),
     "pbvd_last_error": (ctypes.c_char_p, []),
 }
@@ -326,3 +343,73 @@ class Batch:
                "pbvd_batch_info")
         return dict(zip(("tiles", "blocks", "forward_stages", "workspace_bytes"),
                         (x.value for x in v)))
+
+
+class Server:
+    """pbvd_server_*: continuous batching of decode requests (host in/out).
+
+    ``codes`` as for :class:`Batch`.  ``submit`` copies the symbols and
+    returns a ticket; ``wait`` returns (packed bits, timing dict)."""
+
+    def __init__(self, codes, device_bytes: int = 256 << 20, max_inflight: int = 4,
+                 max_batch_frames: int = 1024, max_queued: int = 1 << 20):
+        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16)
+        self.codes = [{**defaults, **c} for c in codes]
+        arr = (pbvd_code * len(codes))(*[_code_struct(**c) for c in self.codes])
+        cfg = pbvd_server_config(int(device_bytes), int(max_inflight), int(max_batch_frames),
+                                 int(max_queued))
+        h = ctypes.c_void_p()
+        _check(lib().pbvd_server_create(ctypes.cast(arr, ctypes.c_void_p), len(codes),
+                                        ctypes.byref(cfg), ctypes.byref(h)), "pbvd_server_create")
+        self.handle = h.value
+        self._pending = {}   # ticket -> (out array, n_bits, symbols kept alive)
+
+    def close(self):
+        if self.handle:
+            lib().pbvd_server_destroy(ctypes.c_void_p(self.handle))
+            self.handle = None
+            self._pending.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, code: int, syms: np.ndarray, n_bits: int) -> int:
+        syms = np.ascontiguousarray(syms, dtype=np.uint8)
+        c = self.codes[code]
+        need = (n_bits + (c["K"] - 1 if c["terminated"] else 0)) * len(c["gens"])
+        if syms.size < need:
+            raise ValueError("syms has %d bytes, needs %d" % (syms.size, need))
+        out = np.zeros((n_bits + 7) // 8, dtype=np.uint8)
+        t = ctypes.c_int64()
+        _check(lib().pbvd_server_submit(ctypes.c_void_p(self.handle), int(code),
+                                        syms.ctypes.data_as(ctypes.c_void_p), int(n_bits),
+                                        out.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t)),
+               "pbvd_server_submit")
+        self._pending[t.value] = (out, n_bits)
+        return t.value
+
+    def wait(self, ticket: int, timeout_us: int = -1):
+        info = pbvd_request_info()
+        st = lib().pbvd_server_wait(ctypes.c_void_p(self.handle), int(ticket), int(timeout_us),
+                                    ctypes.byref(info))
+        if st == PBVD_EAGAIN:
+            return None
+        out, _ = self._pending.pop(ticket, (None, 0))
+        _check(st, "pbvd_server_wait")
+        return out, dict(submit_ns=info.submit_ns, start_ns=info.start_ns, done_ns=info.done_ns,
+                         batch_frames=info.batch_frames, latency_ns=info.done_ns - info.submit_ns)
+
+    def counters(self):
+        v = [ctypes.c_int64() for _ in range(3)]
+        _check(lib().pbvd_server_counters(ctypes.c_void_p(self.handle),
+                                          *[ctypes.byref(x) for x in v]), "pbvd_server_counters")
+        return dict(zip(("batches", "requests_done", "peak_inflight"), (x.value for x in v)))

@@ -121,3 +121,21 @@ def test_batch_rejects_bad_frames(pbvd):
             assert ei.value.status == pbvd.PBVD_EINVAL
     with pytest.raises(pbvd.PbvdError):
         pbvd.Batch([dict(K=7, gens=(0o171, 0o133), D=100, L=42)])  # D % 8 != 0
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(max_inflight=0), dict(max_inflight=9), dict(max_batch_frames=0), dict(max_queued=0),
+    dict(device_bytes=1 << 19),
+])
+def test_server_config_validation(pbvd, cfg):
+    args = dict(device_bytes=64 << 20, max_inflight=2, max_batch_frames=16, max_queued=100)
+    args.update(cfg)
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Server([dict(K=7, gens=(0o171, 0o133), D=64, L=42)], **args)
+    assert ei.value.status == pbvd.PBVD_EINVAL
+
+
+def test_server_rejects_bad_codes(pbvd):
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Server([dict(K=7, gens=(0o171, 0o133), D=60, L=42)])
+    assert ei.value.status == pbvd.PBVD_EINVAL

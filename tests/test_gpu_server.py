@@ -1,0 +1,103 @@
+"""Request server (continuous batching): every request's bits equal the
+oracle's and decoding the same request alone; admission by the device
+budget; several submitting threads."""
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00066_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+CODES = [dict(K=7, gens=(0o171, 0o133), D=64, L=42),
+         dict(K=7, gens=(0o133, 0o171, 0o165), D=64, L=42),
+         dict(K=9, gens=(0o557, 0o663, 0o711), D=64, L=54)]
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def pbvd():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1608_00066_amd import pbvd as mod
+    mod.lib()
+    return mod
+
+
+def oracle_bits(c, st):
+    c = {**dict(terminated=True, input_kind=0), **c}
+    return oracle.decode(c["K"], c["gens"], c["D"], c["L"], st["syms"], st["n"],
+                         terminated=c["terminated"], input_kind=c["input_kind"])["bits"]
+
+
+def unpack(out, n):
+    return np.unpackbits(out, bitorder="little")[:n]
+
+
+def test_server_mix_equals_alone_and_oracle(pbvd):
+    reqs = datagen.make_requests(CODES, 150, seed=501, median=400, hi=5000)
+    log("server: 150 requests, 3 codes, median 400 bits")
+    with pbvd.Server(CODES, device_bytes=128 << 20, max_inflight=3, max_batch_frames=64) as srv:
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        cnt = srv.counters()
+        log("counters %s" % cnt)
+        assert cnt["requests_done"] == len(reqs)
+        alone = []
+        for ci, st in reqs:
+            alone.append(srv.wait(srv.submit(ci, st["syms"], st["n"])))
+    for (ci, st), (m, mi), (a, ai) in zip(reqs, mixed, alone):
+        assert ai["batch_frames"] == 1
+        assert np.array_equal(m, a), "request differs alone and in the mix"
+        bits = unpack(m, st["n"])
+        ref = oracle_bits(CODES[ci], st)
+        assert np.array_equal(bits, ref), "request of %d bits (code %d) differs from the oracle" % (st["n"], ci)
+        assert np.all(np.unpackbits(m, bitorder="little")[st["n"]:] == 0)
+    assert max(i["batch_frames"] for _, i in mixed) > 1
+
+
+def test_server_small_budget_many_batches(pbvd):
+    reqs = datagen.make_requests(CODES[:1], 60, seed=502, median=2000, hi=6000)
+    log("server: 1 MiB per batch, 60 requests")
+    with pbvd.Server(CODES[:1], device_bytes=2 << 20, max_inflight=2, max_batch_frames=1000) as srv:
+        with pytest.raises(pbvd.PbvdError) as ei:  # alone exceeds a batch's budget
+            big = datagen.make_stream(7, (0o171, 0o133), 60000, 3.0, seed=1)
+            srv.submit(0, big["syms"], big["n"])
+        assert ei.value.status == pbvd.PBVD_EINVAL
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        res = [srv.wait(t) for t in tickets]
+        cnt = srv.counters()
+        log("counters %s" % cnt)
+        assert cnt["batches"] > 2
+    for (ci, st), (out, _) in zip(reqs, res):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(CODES[ci], st))
+
+
+def test_server_concurrent_submitters(pbvd):
+    reqs = datagen.make_requests(CODES[:2], 200, seed=503, median=300, hi=3000)
+    results = [None] * len(reqs)
+    errors = []
+    with pbvd.Server(CODES[:2], device_bytes=64 << 20, max_inflight=4, max_batch_frames=32) as srv:
+        def run(k):
+            try:
+                for i in range(k, len(reqs), 4):
+                    ci, st = reqs[i]
+                    results[i] = srv.wait(srv.submit(ci, st["syms"], st["n"]))[0]
+            except Exception as e:  # reported below
+                errors.append(e)
+        th = [threading.Thread(target=run, args=(k,)) for k in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=120)
+        assert not any(t.is_alive() for t in th)
+    assert not errors, errors
+    for (ci, st), out in zip(reqs, results):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(CODES[ci], st))
