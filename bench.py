@@ -107,6 +107,129 @@ def cpu_baseline(st, K, gens, D, L, target_s: float):
                       "%.1f s" % (count, nb_total, bits, dt)}
 
 
+def plain_per_frame(torch, pbvd, codes, frames, syms, out, reps: int = 1):
+    """Seconds of decoding every frame with its own pbvd_decode call (one
+    launch per frame, one plan per code), median of `reps` passes."""
+    import ctypes
+    L = pbvd.lib()
+    plans = [pbvd.Plan(c["K"], c["gens"], c["D"], c["L"]) for c in codes]
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    bs, bo = syms.data_ptr(), out.data_ptr()
+    calls = [(ctypes.c_void_p(plans[ci].handle), ctypes.c_void_p(bs + so), n, ctypes.c_void_p(bo + oo))
+             for (so, n, oo, ci) in frames]
+
+    def one_pass():
+        for h, sp, n, op in calls:
+            if L.pbvd_decode(h, sp, n, op, stream) != 0:
+                raise RuntimeError("pbvd_decode failed: " + pbvd.pbvd_last_error())
+    one_pass()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        one_pass()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e-3)
+    for p in plans:
+        p.close()
+    return sorted(ts)[len(ts) // 2]
+
+
+def bench_batched(torch, steps: int):
+    """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
+    50/50, Eb/N0 U[1, 5] dB): D tuned, HIP-graph replay timed, against one
+    plain launch per frame."""
+    from paper_1608_00066_amd import autotune, datagen, pbvd
+    base = [dict(K=7, gens=(0o171, 0o133), L=42), dict(K=7, gens=(0o133, 0o171, 0o165), L=42)]
+    frames, streams, syms_h, out_bytes = datagen.make_frames(
+        [dict(c, D=512) for c in base], 4096, 40, 6144, seed=datagen.config_seed(3, 0, 0))
+    n_bits = sum(f[1] for f in frames)
+    syms = torch.from_numpy(syms_h).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    codes, table = autotune.tune_batch_d(torch, base, frames, syms, out)
+    D = codes[0]["D"]
+    log("batched: tuned D=%d" % D)
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.numel(), out.numel())
+        info = b.info()
+        b.decode(syms, out)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(g, stream=side):
+                b.decode(syms, out)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            g.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in ev:
+            e0.record()
+            g.replay()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        dev = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps * 1e-3
+        del g
+    batched = out.clone()
+    log("batched: plain per-frame launches")
+    t_plain_512 = plain_per_frame(torch, pbvd, [dict(c, D=512) for c in base], frames, syms, out)
+    t_plain_d = plain_per_frame(torch, pbvd, codes, frames, syms, out)
+    same = bool(torch.equal(out, batched))
+    ops = 4.0 * info["forward_stages"] * 64
+    return {
+        "workload": "4096 zero-terminated frames, info bits U[40,6144], K=7 r1/2 (171,133) and "
+                    "r1/3 (133,171,165) 50/50, int8 soft at Eb/N0 U[1,5] dB, L=42",
+        "n_bits": n_bits, "D": D, "tiles": info["tiles"],
+        "batched_graph_ms": round(wall * 1e3, 4), "batched_event_ms": round(dev * 1e3, 4),
+        "batched_mbps": round(n_bits / wall / 1e6, 1),
+        "batched_alu_frac": round(ops / dev / PEAK_ALU_OPS[16], 4),
+        "plain_per_frame_d512_mbps": round(n_bits / t_plain_512 / 1e6, 2),
+        "plain_per_frame_same_d_mbps": round(n_bits / t_plain_d / 1e6, 2),
+        "speedup_vs_plain_d512": round(t_plain_512 / wall, 1),
+        "batched_equals_plain_same_d": same,
+        "tuning_ms": {str(d): round(t * 1e3, 4) for d, t, _ in table},
+    }
+
+
+def bench_serving(seconds: float, rates=(2000, 5000, 10000, 20000, 50000)):
+    """Request server under Poisson arrivals: lengths log-normal (median
+    1500, sigma 1, clipped to [40, 65536]), codes K=7 r1/2, K=7 r1/3 and
+    K=9 r1/3 uniform, Eb/N0 U[1, 5] dB; D tuned for p99 at 10k requests/s."""
+    from paper_1608_00066_amd import autotune, datagen, pbvd
+    base = [dict(K=7, gens=(0o171, 0o133), L=42), dict(K=7, gens=(0o133, 0o171, 0o165), L=42),
+            dict(K=9, gens=(0o557, 0o663, 0o711), L=54)]
+    pools = {}
+
+    def pool_for(cs):
+        # the symbols do not depend on D: one pool serves every candidate
+        if "p" not in pools:
+            pools["p"] = datagen.make_requests(cs, 1500, seed=datagen.config_seed(4, 0, 0))
+        return pools["p"]
+    kw = dict(device_bytes=1 << 30, max_inflight=4, max_batch_frames=4096)
+    codes, table = autotune.tune_server_d(base, pool_for, 10000, seconds=0.5, **kw)
+    res = {"workload": "Poisson arrivals, 1500-request pool, info bits log-normal(median 1500, "
+                       "sigma 1) clipped to [40,65536], K=7 r1/2, K=7 r1/3, K=9 r1/3 uniform, "
+                       "Eb/N0 U[1,5] dB, L=6K; %.1f s per rate" % seconds,
+           "D": codes[0]["D"], "max_inflight": kw["max_inflight"],
+           "device_bytes": kw["device_bytes"],
+           "tuning_p99_ms": {str(d): r["p99_ms"] for d, r in table}, "rates": []}
+    with pbvd.Server(codes, **kw) as srv:
+        pool = pool_for(codes)
+        autotune.serve_load(srv, pool, rates[0], 0.2, seed=0)
+        for r in rates:
+            log("serving: %d requests/s" % r)
+            res["rates"].append(autotune.serve_load(srv, pool, r, seconds, seed=r))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +240,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the secondary K=9 and 2^20-bit measurements")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
+                    help="seconds of Poisson load per arrival rate in the serving measurement")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters of rocprofv3) and exit")
@@ -175,6 +300,16 @@ def main():
                 ms2, kms2 = time_decode(torch, p2, d_s2, n2, o2, max(3, args.steps // 4), 2)
             extras[tag + "_mbps"] = round(n2 / (ms2 * 1e-3) / 1e6, 1)
             del d_s2, o2, s2
+        sweep = {}
+        for d2 in (256, 1024, 2048):
+            with pbvd.Plan(K, gens, d2, L, True, datagen.SOFT_I8, 16) as p2:
+                ms2, _ = time_decode(torch, p2, syms, n, out, max(3, args.steps // 4), 2)
+            sweep[str(d2)] = round(n / (ms2 * 1e-3) / 1e6, 1)
+        extras["k7_r2_2p%d_mbps_by_d" % args.log2_bits] = sweep
+        log("batched decoding")
+        extras["batched"] = bench_batched(torch, args.steps)
+        log("serving")
+        extras["serving"] = bench_serving(args.serve_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -116,6 +116,27 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
                            int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
                            void *hip_stream);
 
+/* pbvd_decode_host flag: both host buffers are page-locked (e.g. from
+ * hipHostMalloc), so chunks are copied by DMA straight from and to them. */
+#define PBVD_HOST_PINNED 1u
+
+/* Decode a whole stream held in host memory, overlapping transfers with
+ * decoding (Sec. IV-C, Eq. 7).  The PBs are cut into chunks of chunk_pbs PBs
+ * (0: about 2 chunks per stream); chunk c goes to the device (its symbols
+ * with the L-stage overlap on both sides), is decoded, and its bits come
+ * back on stream c mod n_streams, so the copies of one chunk overlap the
+ * decoding of others.  Bits equal pbvd_decode of the same stream.
+ *   h_syms    : host, (n_bits + terminated*(K-1))*R bytes, stage-major
+ *   h_out     : host, ceil(n_bits/8) bytes, written completely
+ *   n_streams : 1..8 HIP streams (owned by the plan, created on first use)
+ *   chunk_pbs : >= 0; chunk_pbs * D must be a multiple of 8
+ *   flags     : PBVD_HOST_PINNED, or 0 for pageable buffers, which are staged
+ *               through pinned buffers the plan allocates
+ * Synchronous: returns when h_out is complete.  Device buffers of the chunks
+ * are owned by the plan and freed by pbvd_destroy. */
+pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
+                             int32_t n_streams, int64_t chunk_pbs, uint32_t flags);
+
 /* Number of parallel blocks of a stream: ceil(n_bits / D); 0 if n_bits < 1. */
 int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits);
 

@@ -1,22 +1,26 @@
-"""Autotuner of the batched decoder: picks the block length D of each code
-for a given set of frames by timing pbvd_batch_decode on the device.
+"""Tuning and load helpers of the batched decoder and the request server.
 
-D changes which bits the decoder returns (Sec. III-A: a PB sees only L
-stages beyond its decoded range), so the tuner only chooses among the
-candidate D values given to it, with L fixed by the caller (6K keeps the
-error rate at the full-frame level, Sec. V); results are compared with the
-oracle run with the chosen D and L.  D >= the longest frame decodes every
-frame as one block (full-frame Viterbi)."""
+The block length D changes which bits the decoder returns (Sec. III-A: a PB
+sees only L stages beyond its decoded range), so the tuners only choose among
+the candidate D values given to them, with L fixed by the caller (about 6K
+keeps the error rate at the full-frame level, Sec. V); results are compared
+with the oracle run with the chosen D and L.  D at least the longest frame
+decodes every frame as one block (full-frame Viterbi).
+
+Throughput tuning times pbvd_batch_decode on the device; latency tuning
+drives a pbvd_server with Poisson arrivals and takes the 99th percentile."""
 from __future__ import annotations
 
-import itertools
 import time
 
-from . import pbvd
+import numpy as np
+
+from . import datagen, pbvd
 
 
 def time_batch(torch, codes, frames, syms_dev, out_dev, reps: int = 5, warmup: int = 2):
-    """Median seconds of one pbvd_batch_decode of `frames` with `codes`."""
+    """Median seconds of one pbvd_batch_decode of `frames` with `codes`,
+    and the batch's work-list statistics."""
     with pbvd.Batch(codes) as b:
         b.set_frames(frames, syms_dev.numel(), out_dev.numel())
         for _ in range(warmup):
@@ -35,25 +39,62 @@ def time_batch(torch, codes, frames, syms_dev, out_dev, reps: int = 5, warmup: i
         return ts[len(ts) // 2], b.info()
 
 
-def tune(torch, codes, frames, syms_dev, out_dev, d_candidates=(128, 256, 512, 1024, 2048),
-         reps: int = 5, joint: bool = False):
-    """Returns (best code list with D filled in, table of (D tuple, seconds))."""
+def tune_batch_d(torch, codes, frames, syms_dev, out_dev,
+                 d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512), reps: int = 5):
+    """One D for all codes, the fastest batched decode of `frames`.
+    Returns (codes with D filled in, [(D, seconds, info)])."""
     table = []
-    if joint:
-        combos = list(itertools.product(d_candidates, repeat=len(codes)))
-    else:
-        combos = [tuple([d] * len(codes)) for d in d_candidates]
-    for ds in combos:
-        cs = [dict(c, D=int(d)) for c, d in zip(codes, ds)]
+    for d in d_candidates:
+        cs = [dict(c, D=int(d)) for c in codes]
         t, info = time_batch(torch, cs, frames, syms_dev, out_dev, reps=reps)
-        table.append((ds, t, info))
-    best = min(table, key=lambda r: r[1])
-    return [dict(c, D=int(d)) for c, d in zip(codes, best[0])], table
+        table.append((int(d), t, info))
+    best = min(table, key=lambda r: r[1])[0]
+    return [dict(c, D=best) for c in codes], table
 
 
-def wall_seconds(fn, torch):
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    fn()
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0
+def serve_load(srv, pool, rate: float, seconds: float, seed: int = 1):
+    """Submit requests drawn from `pool` ((code, stream) pairs) to a
+    pbvd.Server at Poisson arrival times of the given rate for `seconds`,
+    wait for all, and return latency percentiles (ms), decoded Mbps over
+    the span from the first submission to the last completion, and the mean
+    batch size."""
+    rng = np.random.default_rng(seed)
+    n = max(1, int(rate * seconds))
+    arrivals = datagen.poisson_arrivals(rng, n, rate)
+    pick = rng.integers(0, len(pool), size=n)
+    tickets = []
+    bits = 0
+    start = time.perf_counter()
+    for k in range(n):
+        target = start + arrivals[k]
+        while time.perf_counter() < target:
+            pass
+        ci, st = pool[pick[k]]
+        tickets.append(srv.submit(ci, st["syms"], st["n"]))
+        bits += st["n"]
+    submitted = time.perf_counter()
+    infos = [srv.wait(t)[1] for t in tickets]
+    lat = np.array([i["latency_ns"] for i in infos], dtype=np.float64) / 1e6
+    span = (max(i["done_ns"] for i in infos) - min(i["submit_ns"] for i in infos)) / 1e9
+    return {"rate": rate, "requests": n, "offered_rate": round(n / (submitted - start), 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 4),
+            "p99_ms": round(float(np.percentile(lat, 99)), 4),
+            "max_ms": round(float(lat.max()), 4),
+            "mbps": round(bits / span / 1e6, 2),
+            "mean_batch": round(float(np.mean([i["batch_frames"] for i in infos])), 2)}
+
+
+def tune_server_d(codes, pool_for, rate: float, seconds: float = 0.5, d_candidates=(32, 64, 128),
+                  **server_kw):
+    """One D for all codes, the lowest p99 latency at `rate`.  pool_for(codes)
+    returns the request pool for codes with D set.  Returns (codes with D
+    filled in, [(D, load result)])."""
+    table = []
+    for d in d_candidates:
+        cs = [dict(c, D=int(d)) for c in codes]
+        with pbvd.Server(cs, **server_kw) as srv:
+            pool = pool_for(cs)
+            serve_load(srv, pool, rate, 0.1, seed=0)
+            table.append((int(d), serve_load(srv, pool, rate, seconds, seed=1)))
+    best = min(table, key=lambda r: r[1]["p99_ms"])[0]
+    return [dict(c, D=best) for c in codes], table

@@ -8,6 +8,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "pbvd.h"
@@ -202,6 +203,41 @@ CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int6
 
 }  // namespace
 
+namespace {
+
+// Device scratch of one decode in flight: survivor rows of one launch and the
+// output staging words (used when D % 32 != 0 or the output is unaligned).
+struct Workspace {
+    uint32_t *sp = nullptr;
+    size_t sp_bytes = 0;
+    uint32_t *words = nullptr;
+    size_t words_bytes = 0;
+};
+
+void free_workspace(Workspace &w) {
+    if (w.sp) (void)hipFree(w.sp);
+    if (w.words) (void)hipFree(w.words);
+    w = Workspace{};
+}
+
+constexpr int kMaxPipeStreams = 8;
+
+// Host-buffer decoding (pbvd_decode_host): per stream a workspace, device
+// chunk buffers and pinned staging, grown on demand.
+struct PipeStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    Workspace ws;
+    uint8_t *d_in = nullptr, *d_out = nullptr;
+    size_t d_in_bytes = 0, d_out_bytes = 0;
+    uint8_t *h_in = nullptr, *h_out = nullptr;    // pinned staging
+    size_t h_in_bytes = 0, h_out_bytes = 0;
+    // chunk whose bits still wait in h_out (staged mode)
+    int64_t pend_byte = -1, pend_bytes = 0;
+};
+
+}  // namespace
+
 struct pbvd_plan {
     pbvd_code code;
     int code_idx;
@@ -210,10 +246,8 @@ struct pbvd_plan {
     int row_stages;           // stages per stored row
     int64_t sp_wave_dwords;   // survivor dwords per wave slot
     int64_t budget_bytes;     // survivor workspace limit
-    uint32_t *sp;
-    size_t sp_bytes;
-    uint32_t *words;
-    size_t words_bytes;
+    Workspace ws;             // pbvd_decode / pbvd_decode_ex
+    PipeStream pipe[kMaxPipeStreams];
 };
 
 namespace {
@@ -237,9 +271,9 @@ pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits
 }
 
 // Runs the decode kernels of one call; fills *geo with the decomposition.
-pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
-                       int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm, hipStream_t stream,
-                       CallGeometry *geo_out, bool single_launch) {
+pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
+                       int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
+                       hipStream_t stream, CallGeometry *geo_out, bool single_launch) {
     const pbvd_code &c = p->code;
     const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count);
     if (geo_out) *geo_out = g;
@@ -251,7 +285,7 @@ pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t
     if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
 
     const int64_t launch_waves = g.n_waves < per_launch ? g.n_waves : per_launch;
-    pbvd_status st = ensure_buffer(&p->sp, &p->sp_bytes,
+    pbvd_status st = ensure_buffer(&ws.sp, &ws.sp_bytes,
                                    (size_t)(launch_waves * p->sp_wave_dwords * 4), "survivors");
     if (st != PBVD_OK) return st;
 
@@ -259,9 +293,9 @@ pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t
     const bool direct = (c.D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
     if (!direct) {
         const int64_t nwords = ceil_div(g.out_bits, 32) + 2;
-        st = ensure_buffer(&p->words, &p->words_bytes, (size_t)nwords * 4, "output staging");
+        st = ensure_buffer(&ws.words, &ws.words_bytes, (size_t)nwords * 4, "output staging");
         if (st != PBVD_OK) return st;
-        hipError_t e = pbvd::fill_u32(p->words, nwords, 0u, stream);
+        hipError_t e = pbvd::fill_u32(ws.words, nwords, 0u, stream);
         if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
     }
 
@@ -269,9 +303,9 @@ pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t
     pbvd::KernelArgs &a = req.args;
     a.syms = (const uint8_t *)d_syms;
     a.out = d_out;
-    a.out_words = direct ? nullptr : p->words;
+    a.out_words = direct ? nullptr : ws.words;
     a.final_pm = d_final_pm;
-    a.sp = p->sp;
+    a.sp = ws.sp;
     a.n = n_bits;
     a.T = g.T;
     a.pb_first = pb_first;
@@ -297,7 +331,7 @@ pbvd_status run_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t
         if (e != hipSuccess) return fail_hip(e, "decode kernel launch");
     }
     if (!direct) {
-        hipError_t e = pbvd::words_to_bytes(p->words, d_out, out_bytes, stream);
+        hipError_t e = pbvd::words_to_bytes(ws.words, d_out, out_bytes, stream);
         if (e != hipSuccess) return fail_hip(e, "output copy launch");
     }
     return PBVD_OK;
@@ -337,7 +371,7 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
     if (st != PBVD_OK || pb_count == 0) return st;
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
-    return run_decode(p, d_syms, n_bits, pb_first, pb_count, d_out_bits, d_final_pm,
+    return run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, d_final_pm,
                       (hipStream_t)hip_stream, nullptr, false);
 }
 
@@ -387,10 +421,10 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
     hipStream_t s = (hipStream_t)hip_stream;
     CallGeometry g{};
-    st = run_decode(p, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true);
+    st = run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true);
     if (st != PBVD_OK || pb_count == 0) return st;
     pbvd::SurvivorView v{};
-    v.sp = p->sp;
+    v.sp = p->ws.sp;
     v.sp_wave_dwords = p->sp_wave_dwords;
     v.T = g.T;
     v.pb_first = pb_first;
@@ -425,13 +459,139 @@ pbvd_status pbvd_debug_branch_metrics(pbvd_plan *p, const void *d_syms, int64_t 
     return PBVD_OK;
 }
 
+pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
+                             int32_t n_streams, int64_t chunk_pbs, uint32_t flags) {
+    g_last_error[0] = 0;
+    if (!p) return fail(PBVD_EINVAL, "plan is NULL");
+    if (!h_syms || !h_out) return fail(PBVD_EINVAL, "NULL host buffer");
+    if (n_bits < 1) return fail(PBVD_EINVAL, "n_bits must be >= 1 (got %lld)", (long long)n_bits);
+    if (n_streams < 1 || n_streams > kMaxPipeStreams)
+        return fail(PBVD_EINVAL, "n_streams must be in [1, %d]", kMaxPipeStreams);
+    if (flags & ~(uint32_t)PBVD_HOST_PINNED) return fail(PBVD_EINVAL, "unknown flags 0x%x", flags);
+    const pbvd_code &c = p->code;
+    const int64_t D = c.D, L = c.L, R = c.R;
+    const int64_t nb = ceil_div(n_bits, D);
+    const int64_t T = n_bits + (c.terminated ? c.K - 1 : 0);
+    // chunks start on byte boundaries of the output
+    int64_t g = D, e8 = 8;
+    while (e8) { const int64_t t = g % e8; g = e8; e8 = t; }
+    const int64_t unit = 8 / g;
+    if (chunk_pbs < 0) return fail(PBVD_EINVAL, "chunk_pbs must be >= 0");
+    if (chunk_pbs == 0) chunk_pbs = ceil_div(ceil_div(nb, 2 * (int64_t)n_streams), unit) * unit;
+    if (chunk_pbs % unit != 0)
+        return fail(PBVD_EINVAL, "chunk_pbs * D must be a multiple of 8 (chunk_pbs %% %lld != 0)", (long long)unit);
+    if (chunk_pbs > nb) chunk_pbs = ceil_div(nb, unit) * unit;
+    const bool pinned = (flags & PBVD_HOST_PINNED) != 0;
+    const int64_t n_chunks = ceil_div(nb, chunk_pbs);
+    const int used = (int)std::min<int64_t>(n_streams, n_chunks);
+    // the kernels read up to a dword before a PB's first symbol and up to
+    // one trip's window past its last one: pad the chunk buffer on both sides
+    constexpr int64_t kPad = 256;
+    const int64_t in_max = (chunk_pbs * D + 2 * L) * R + 2 * kPad;
+    const int64_t out_max = ceil_div(chunk_pbs * D, 8) + 8;
+    if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
+    for (int si = 0; si < used; ++si) {
+        PipeStream &ps = p->pipe[si];
+        hipError_t e = hipSuccess;
+        if (!ps.stream) e = hipStreamCreateWithFlags(&ps.stream, hipStreamNonBlocking);
+        if (e == hipSuccess && !ps.done) e = hipEventCreateWithFlags(&ps.done, hipEventDisableTiming);
+        if (e != hipSuccess) return fail_hip(e, "pipeline stream creation");
+        pbvd_status st = ensure_buffer(reinterpret_cast<uint32_t **>(&ps.d_in), &ps.d_in_bytes, (size_t)in_max, "chunk input");
+        if (st == PBVD_OK)
+            st = ensure_buffer(reinterpret_cast<uint32_t **>(&ps.d_out), &ps.d_out_bytes, (size_t)out_max, "chunk output");
+        if (st != PBVD_OK) return st;
+        if (!pinned) {
+            if (ps.h_in_bytes < (size_t)in_max) {
+                if (ps.h_in) (void)hipHostFree(ps.h_in);
+                ps.h_in = nullptr;
+                ps.h_in_bytes = 0;
+                e = hipHostMalloc((void **)&ps.h_in, (size_t)in_max, hipHostMallocDefault);
+                if (e != hipSuccess) return fail_hip(e, "pinned staging");
+                ps.h_in_bytes = (size_t)in_max;
+            }
+            if (ps.h_out_bytes < (size_t)out_max) {
+                if (ps.h_out) (void)hipHostFree(ps.h_out);
+                ps.h_out = nullptr;
+                ps.h_out_bytes = 0;
+                e = hipHostMalloc((void **)&ps.h_out, (size_t)out_max, hipHostMallocDefault);
+                if (e != hipSuccess) return fail_hip(e, "pinned staging");
+                ps.h_out_bytes = (size_t)out_max;
+            }
+        }
+        ps.pend_byte = -1;
+    }
+    const uint8_t *hs = (const uint8_t *)h_syms;
+    bool busy[kMaxPipeStreams] = {};
+    pbvd_status result = PBVD_OK;
+    for (int64_t ch = 0; ch < n_chunks && result == PBVD_OK; ++ch) {
+        PipeStream &ps = p->pipe[ch % used];
+        const int64_t pb0 = ch * chunk_pbs;
+        const int64_t pbn = std::min(chunk_pbs, nb - pb0);
+        const int64_t f0 = std::max<int64_t>(0, pb0 * D - L);
+        const int64_t f1 = std::min(T, (pb0 + pbn) * D + L);
+        const int64_t in_bytes = (f1 - f0) * R;
+        const int64_t out_bits = std::min(n_bits, (pb0 + pbn) * D) - pb0 * D;
+        const int64_t out_bytes = ceil_div(out_bits, 8);
+        const int64_t byte0 = pb0 * D / 8;
+        const uint8_t *src = hs + f0 * R;
+        if (!pinned) {
+            // reuse this stream's staging: its previous chunk must be done
+            if (busy[ch % used]) {
+                hipError_t e = hipEventSynchronize(ps.done);
+                if (e != hipSuccess) return fail_hip(e, "pipeline wait");
+                if (ps.pend_byte >= 0) memcpy(h_out + ps.pend_byte, ps.h_out, (size_t)ps.pend_bytes);
+                ps.pend_byte = -1;
+            }
+            memcpy(ps.h_in, src, (size_t)in_bytes);
+            src = ps.h_in;
+        }
+        hipError_t e = hipMemcpyAsync(ps.d_in + kPad, src, (size_t)in_bytes, hipMemcpyHostToDevice, ps.stream);
+        if (e != hipSuccess) return fail_hip(e, "chunk upload");
+        // stage 0 of the stream at a virtual address: the chunk's stages [f0, f1) land in d_in
+        const uint8_t *base = ps.d_in + kPad - f0 * R;
+        result = run_decode(p, ps.ws, base, n_bits, pb0, pbn, ps.d_out, nullptr, ps.stream, nullptr, false);
+        if (result != PBVD_OK) break;
+        uint8_t *dst = pinned ? h_out + byte0 : ps.h_out;
+        e = hipMemcpyAsync(dst, ps.d_out, (size_t)out_bytes, hipMemcpyDeviceToHost, ps.stream);
+        if (e == hipSuccess) e = hipEventRecord(ps.done, ps.stream);
+        if (e != hipSuccess) return fail_hip(e, "chunk read-back");
+        busy[ch % used] = true;
+        if (!pinned) {
+            ps.pend_byte = byte0;
+            ps.pend_bytes = out_bytes;
+        }
+    }
+    for (int si = 0; si < used; ++si) {
+        PipeStream &ps = p->pipe[si];
+        if (!busy[si]) continue;
+        hipError_t e = hipEventSynchronize(ps.done);
+        if (e != hipSuccess && result == PBVD_OK) result = fail_hip(e, "pipeline wait");
+        if (result == PBVD_OK && !pinned && ps.pend_byte >= 0)
+            memcpy(h_out + ps.pend_byte, ps.h_out, (size_t)ps.pend_bytes);
+        ps.pend_byte = -1;
+    }
+    return result;
+}
+
 void pbvd_destroy(pbvd_plan *p) {
     if (!p) return;
     {
         DeviceGuard dg(p->device);
-        if (p->sp || p->words) (void)hipDeviceSynchronize();
-        if (p->sp) (void)hipFree(p->sp);
-        if (p->words) (void)hipFree(p->words);
+        bool any = p->ws.sp || p->ws.words;
+        for (const PipeStream &ps : p->pipe) any = any || ps.stream;
+        if (any) (void)hipDeviceSynchronize();
+        free_workspace(p->ws);
+        for (PipeStream &ps : p->pipe) {
+            free_workspace(ps.ws);
+            if (ps.d_in) (void)hipFree(ps.d_in);
+            if (ps.d_out) (void)hipFree(ps.d_out);
+            if (ps.h_in) (void)hipHostFree(ps.h_in);
+            if (ps.h_out) (void)hipHostFree(ps.h_out);
+            if (ps.done) (void)hipEventDestroy(ps.done);
+            if (ps.stream) (void)hipStreamDestroy(ps.stream);
+        }
     }
     delete p;
 }

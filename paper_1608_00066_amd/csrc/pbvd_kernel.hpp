@@ -291,10 +291,13 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
         } else {
             dd[X] = P::diff(a, b);
             if constexpr (X & 1) {
-                // sign bytes of registers X-1 and X: [lo(X-1), hi(X-1), lo(X), hi(X)]
-                const uint32_t p = __builtin_amdgcn_perm(dd[X], dd[X - 1], 0x07050301u);
+                // selectors 8..11 of v_perm_b32 replicate bits 15, 31, 47, 63
+                // of {dd[X], dd[X-1]} over a byte: the four signs
+                // [lo(X-1), hi(X-1), lo(X), hi(X)] as 0x00 / 0xff bytes, so
+                // any bit of a byte can take the decision without a shift
+                const uint32_t p = __builtin_amdgcn_perm(dd[X], dd[X - 1], 0x0b0a0908u);
                 constexpr int kk = (X & 15) >> 1;
-                dw[X >> 4] = and_or(p >> (7 - kk), 0x01010101u << kk, dw[X >> 4]);
+                dw[X >> 4] = and_or(p, 0x01010101u << kk, dw[X >> 4]);
             }
         }
     };

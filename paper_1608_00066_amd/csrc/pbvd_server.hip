@@ -96,17 +96,23 @@ struct Footprint {
     int64_t device_bytes(const CodeSet &cs) const { return in_bytes(cs) + align_up(out) + sp_bytes(cs); }
 };
 
+// One batch in flight.  Code 0 of the batch runs on `stream` (which also
+// carries the upload), every other code on its own stream forked after the
+// upload.  Each code reads its own results back and signals its own event,
+// so a code's requests finish without waiting for slower codes of the batch;
+// the slot is free again once every code has finished.
 struct Slot {
     hipStream_t stream = nullptr;
     hipStream_t aux[kMaxCodes] = {};
-    hipEvent_t fork = nullptr, done = nullptr;
-    hipEvent_t join[kMaxCodes] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t done[kMaxCodes] = {};
     uint8_t *dev = nullptr;       // this slot's part of the device arena
     uint8_t *pin_in = nullptr;    // symbols + work list staging
     uint8_t *pin_out = nullptr;   // decoded bits staging
-    std::vector<std::shared_ptr<Request>> reqs;
+    std::vector<std::shared_ptr<Request>> reqs;  // grouped by code
     std::vector<int64_t> out_off;
-    int64_t launch_seq = 0;
+    bool pending[kMaxCodes] = {};  // codes whose results are not back yet
+    int n_pending = 0;
     bool busy = false;
 };
 
@@ -131,7 +137,7 @@ struct pbvd_server {
     std::thread worker;
 
     // counters (under mu)
-    int64_t n_batches = 0, n_done = 0, peak_inflight = 0, launch_seq = 0;
+    int64_t n_batches = 0, n_done = 0, peak_inflight = 0;
 };
 
 namespace {
@@ -140,6 +146,14 @@ namespace {
 pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
     const CodeSet &cs = sv->cs;
     const int64_t n = (int64_t)sl.reqs.size();
+    // group by code (first come first within a code): each code's outputs
+    // are then one contiguous range to read back
+    std::stable_sort(sl.reqs.begin(), sl.reqs.end(),
+                     [](const std::shared_ptr<Request> &a, const std::shared_ptr<Request> &b) {
+                         return a->code < b->code;
+                     });
+    int64_t out_lo[kMaxCodes], out_hi[kMaxCodes];
+    for (int ci = 0; ci < kMaxCodes; ++ci) out_lo[ci] = out_hi[ci] = 0;
     std::vector<pbvd_frame> frames((size_t)n);
     sl.out_off.assign((size_t)n, 0);
     int64_t so = 0, oo = 0;
@@ -148,8 +162,10 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
         memcpy(sl.pin_in + so, r.syms.data(), (size_t)r.sym_bytes);
         frames[(size_t)i] = pbvd_frame{so, r.n_bits, oo, r.code, 0};
         sl.out_off[(size_t)i] = oo;
+        if (i == 0 || sl.reqs[(size_t)i - 1]->code != r.code) out_lo[r.code] = oo;
         so += r.sym_bytes;
         oo += r.out_bytes;
+        out_hi[r.code] = oo;
     }
     const int64_t sym_total = so, out_total = oo;
     WorkList wl;
@@ -195,19 +211,14 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
         st = launch_group(cs, ci, wl.groups[ci], d_syms, sym_total, d_out, d_lanes, d_heads,
                           reinterpret_cast<uint32_t *>(sl.dev + sp_off[ci]), wl.groups[ci].n_tiles, s);
         if (st != PBVD_OK) return st;
-        if (k > 0) {
-            e = hipEventRecord(sl.join[ci], s);
-            if (e != hipSuccess) return fail_hip(e, "join event");
-        }
+        e = hipMemcpyAsync(sl.pin_out + out_lo[ci], d_out + out_lo[ci], (size_t)(out_hi[ci] - out_lo[ci]),
+                           hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return fail_hip(e, "result read-back");
+        e = hipEventRecord(sl.done[ci], s);
+        if (e != hipSuccess) return fail_hip(e, "completion event");
+        sl.pending[ci] = true;
+        sl.n_pending += 1;
     }
-    for (int k = 1; k < n_active; ++k) {
-        e = hipStreamWaitEvent(sl.stream, sl.join[active[k]], 0);
-        if (e != hipSuccess) return fail_hip(e, "join wait");
-    }
-    e = hipMemcpyAsync(sl.pin_out, d_out, (size_t)out_total, hipMemcpyDeviceToHost, sl.stream);
-    if (e != hipSuccess) return fail_hip(e, "result read-back");
-    e = hipEventRecord(sl.done, sl.stream);
-    if (e != hipSuccess) return fail_hip(e, "completion event");
     return PBVD_OK;
 }
 
@@ -227,23 +238,38 @@ void admit(pbvd_server *sv, Slot &sl) {
     sv->queued.store((int64_t)sv->queue.size());
 }
 
-void finish(pbvd_server *sv, Slot &sl, pbvd_status st) {
+// Hands the requests of code `ci` (all codes if ci < 0) back to their callers.
+void finish(pbvd_server *sv, Slot &sl, int ci, pbvd_status st) {
     const int64_t t = now_ns();
-    if (st == PBVD_OK)
-        for (size_t i = 0; i < sl.reqs.size(); ++i)
-            memcpy(sl.reqs[i]->out, sl.pin_out + sl.out_off[i], (size_t)sl.reqs[i]->out_bytes);
+    int64_t count = 0;
+    for (size_t i = 0; i < sl.reqs.size(); ++i) {
+        Request &r = *sl.reqs[i];
+        if (ci >= 0 && r.code != ci) continue;
+        if (st == PBVD_OK) memcpy(r.out, sl.pin_out + sl.out_off[i], (size_t)r.out_bytes);
+        ++count;
+    }
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         for (auto &r : sl.reqs) {
+            if (ci >= 0 && r->code != ci) continue;
             r->status = st;
             r->done_ns = t;
             r->done = true;
         }
-        sv->n_done += (int64_t)sl.reqs.size();
+        sv->n_done += count;
     }
     sv->cv_done.notify_all();
-    sl.reqs.clear();
-    sl.busy = false;
+    if (ci >= 0) {
+        sl.pending[ci] = false;
+        sl.n_pending -= 1;
+    } else {
+        for (int k = 0; k < kMaxCodes; ++k) sl.pending[k] = false;
+        sl.n_pending = 0;
+    }
+    if (sl.n_pending == 0) {
+        sl.reqs.clear();
+        sl.busy = false;
+    }
 }
 
 void worker_main(pbvd_server *sv) {
@@ -257,7 +283,6 @@ void worker_main(pbvd_server *sv) {
             admit(sv, sl);
             if (sl.reqs.empty()) break;  // the head request waits for a slot to drain
             sl.busy = true;
-            sl.launch_seq = ++sv->launch_seq;
             sv->n_batches += 1;
             int inflight = 0;
             for (int k = 0; k < sv->cfg.max_inflight; ++k) inflight += sv->slots[k].busy ? 1 : 0;
@@ -275,8 +300,8 @@ void worker_main(pbvd_server *sv) {
                 st = fail(PBVD_ENOMEM, "host allocation failed while building a batch");
             }
             if (st != PBVD_OK) {
-                (void)hipStreamSynchronize(sl.stream);
-                finish(sv, sl, st);
+                (void)hipDeviceSynchronize();
+                finish(sv, sl, -1, st);
             }
             lk.lock();
         }
@@ -298,14 +323,18 @@ void worker_main(pbvd_server *sv) {
                     any_free = true;
                     continue;
                 }
-                const hipError_t q = hipEventQuery(sl.done);
-                if (q == hipSuccess) {
-                    finish(sv, sl, PBVD_OK);
-                    reaped = true;
-                } else if (q != hipErrorNotReady) {
-                    (void)fail_hip(q, "batch execution");
-                    finish(sv, sl, PBVD_EHIP);
-                    reaped = true;
+                for (int ci = 0; ci < sv->cs.n && sl.busy; ++ci) {
+                    if (!sl.pending[ci]) continue;
+                    const hipError_t q = hipEventQuery(sl.done[ci]);
+                    if (q == hipSuccess) {
+                        finish(sv, sl, ci, PBVD_OK);
+                        reaped = true;
+                    } else if (q != hipErrorNotReady) {
+                        (void)fail_hip(q, "batch execution");
+                        (void)hipDeviceSynchronize();
+                        finish(sv, sl, -1, PBVD_EHIP);
+                        reaped = true;
+                    }
                 }
             }
             if (reaped || (any_free && sv->queued.load() > 0)) break;
@@ -322,10 +351,9 @@ void release(pbvd_server *sv) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         for (int i = 0; i < kMaxCodes; ++i) {
             if (sl.aux[i]) (void)hipStreamDestroy(sl.aux[i]);
-            if (sl.join[i]) (void)hipEventDestroy(sl.join[i]);
+            if (sl.done[i]) (void)hipEventDestroy(sl.done[i]);
         }
         if (sl.fork) (void)hipEventDestroy(sl.fork);
-        if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.pin_in) (void)hipHostFree(sl.pin_in);
         if (sl.pin_out) (void)hipHostFree(sl.pin_out);
     }
@@ -369,10 +397,9 @@ pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pb
             sl.dev = sv->arena + (int64_t)i * sv->slot_bytes;
             e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-            for (int c = 1; c < cs.n && e == hipSuccess; ++c) {
-                e = hipStreamCreateWithFlags(&sl.aux[c], hipStreamNonBlocking);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.join[c], hipEventDisableTiming);
+            for (int c = 0; c < cs.n && e == hipSuccess; ++c) {
+                if (c > 0) e = hipStreamCreateWithFlags(&sl.aux[c], hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done[c], hipEventDisableTiming);
             }
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.pin_in, (size_t)sv->pin_in_bytes, hipHostMallocDefault);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.pin_out, (size_t)sv->pin_out_bytes, hipHostMallocDefault);

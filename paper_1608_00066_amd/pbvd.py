@@ -24,6 +24,7 @@ PBVD_EHIP = -4
 PBVD_EAGAIN = -5
 PBVD_SOFT_I8 = 0
 PBVD_HARD_U8 = 1
+PBVD_HOST_PINNED = 1
 
 
 class pbvd_code(ctypes.Structure):
@@ -64,6 +65,7 @@ SIGNATURES = {
     "pbvd_create": (_I32, [ctypes.POINTER(pbvd_code), ctypes.POINTER(_P)]),
     "pbvd_decode": (_I32, [_P, _P, _I64, _P, _P]),
     "pbvd_decode_ex": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
+    "pbvd_decode_host": (_I32, [_P, _P, _I64, _P, _I32, _I64, ctypes.c_uint32]),
     "pbvd_num_blocks": (_I64, [_P, _I64]),
     "pbvd_block_geometry": (_I32, [_P, _I64, _I64, _I64, _P]),
     "pbvd_debug_survivors": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
@@ -241,6 +243,30 @@ class Plan:
                                   _stream_handle(stream))
         _check(st, "pbvd_decode_ex")
         return out, final_pm
+
+    def decode_host(self, syms, n_bits: int, out=None, n_streams: int = 3, chunk_pbs: int = 0,
+                    pinned: bool = False):
+        """pbvd_decode_host: host symbols (numpy array or pinned CPU tensor) to
+        host packed bits; returns `out` (a new numpy array if None)."""
+        def ptr(a):
+            if hasattr(a, "data_ptr"):
+                if a.is_cuda or not a.is_contiguous():
+                    raise ValueError("host buffers must be contiguous CPU memory")
+                return ctypes.c_void_p(a.data_ptr()), a.numel() * a.element_size()
+            if not (isinstance(a, np.ndarray) and a.flags["C_CONTIGUOUS"]):
+                raise ValueError("host buffers must be contiguous numpy arrays or CPU tensors")
+            return ctypes.c_void_p(a.ctypes.data), a.nbytes
+        nbytes = (n_bits + 7) // 8
+        if out is None:
+            out = np.zeros(nbytes, dtype=np.uint8)
+        sp, sb = ptr(syms)
+        op, ob = ptr(out)
+        if sb < self.stages(n_bits) * self.R or ob < nbytes:
+            raise ValueError("host buffer too small")
+        st = lib().pbvd_decode_host(ctypes.c_void_p(self.handle), sp, n_bits, op, n_streams,
+                                    chunk_pbs, PBVD_HOST_PINNED if pinned else 0)
+        _check(st, "pbvd_decode_host")
+        return out
 
     def debug_survivors(self, syms, n_bits: int, pb_first: int, pb_count: int, stream=None):
         """pbvd_debug_survivors: returns (packed bits, dec[pb_count][D+L][N])."""

@@ -139,3 +139,22 @@ def test_server_rejects_bad_codes(pbvd):
     with pytest.raises(pbvd.PbvdError) as ei:
         pbvd.Server([dict(K=7, gens=(0o171, 0o133), D=60, L=42)])
     assert ei.value.status == pbvd.PBVD_EINVAL
+
+
+def test_decode_host_validation(pbvd):
+    h = pbvd.pbvd_create(7, (0o171, 0o133), 100, 42)
+    try:
+        L = pbvd.lib()
+        syms = np.zeros(4000, dtype=np.uint8)
+        out = np.zeros(250, dtype=np.uint8)
+        sp, op = syms.ctypes.data_as(ctypes.c_void_p), out.ctypes.data_as(ctypes.c_void_p)
+        plan = ctypes.c_void_p(h)
+        assert L.pbvd_decode_host(plan, sp, 1000, op, 0, 0, 0) == -1     # n_streams
+        assert L.pbvd_decode_host(plan, sp, 1000, op, 9, 0, 0) == -1
+        assert L.pbvd_decode_host(plan, sp, 1000, op, 2, 3, 0) == -1     # 3*100 % 8 != 0
+        assert L.pbvd_decode_host(plan, sp, 1000, op, 2, -1, 0) == -1
+        assert L.pbvd_decode_host(plan, sp, 1000, op, 2, 2, 4) == -1     # unknown flag
+        assert L.pbvd_decode_host(plan, None, 1000, op, 2, 2, 0) == -1
+        assert L.pbvd_decode_host(plan, sp, 0, op, 2, 2, 0) == -1
+    finally:
+        pbvd.pbvd_destroy(h)

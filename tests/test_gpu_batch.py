@@ -123,3 +123,38 @@ def test_batch_graph_capture_replays(torch, pbvd):
             torch.cuda.synchronize()
             assert torch.equal(out, eager)
         del g
+
+
+def test_batch_full_size_tuned(torch, pbvd):
+    """The full 4096-frame mixed-code workload at the block length the tuner
+    picks: a sample of frames against the oracle with that D and L, every
+    frame against its own plain decode, bytes between frames untouched."""
+    from paper_1608_00066_amd import autotune
+    base = [dict(K=7, gens=(0o171, 0o133), L=42), dict(K=7, gens=(0o133, 0o171, 0o165), L=42)]
+    frames, streams, syms, out_bytes = make_batch([dict(c, D=512) for c in base], 4096, 40, 6144,
+                                                  seed=datagen.config_seed(3, 0, 0), gap=0)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    codes, _ = autotune.tune_batch_d(torch, base, frames, d_syms, out, d_candidates=(64, 96, 128), reps=3)
+    log("batch full size: tuned D=%d" % codes[0]["D"])
+    out.fill_(0xA5)
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+    host = out.cpu().numpy()
+    rng = np.random.default_rng(3)
+    for f in rng.choice(len(frames), size=400, replace=False):
+        so, n, oo, ci = frames[f]
+        c = codes[ci]
+        ref = oracle.decode(c["K"], c["gens"], c["D"], c["L"], streams[f]["syms"], n)["bits"]
+        got = np.unpackbits(host[oo:oo + (n + 7) // 8], bitorder="little")[:n]
+        assert np.array_equal(got, ref), "frame %d (n=%d, code %d) differs from the oracle" % (f, n, ci)
+    alone = torch.full((out_bytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    plans = [pbvd.Plan(c["K"], c["gens"], c["D"], c["L"]) for c in codes]
+    for (so, n, oo, ci) in frames:
+        plans[ci].decode(d_syms[so:], n, out=alone[oo:oo + (n + 7) // 8])
+    torch.cuda.synchronize()
+    for p in plans:
+        p.close()
+    assert torch.equal(alone, out)

@@ -1,0 +1,62 @@
+"""Host-buffer decoding with transfers overlapped over several streams
+(pbvd_decode_host): bits equal the device-buffer decode and the oracle, for
+pinned and pageable buffers, several stream counts and chunk sizes."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1608_00066_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a ROCm device"
+    return t
+
+
+@pytest.fixture(scope="module")
+def pbvd():
+    from paper_1608_00066_amd import pbvd as mod
+    mod.lib()
+    return mod
+
+
+CASES = [
+    # K, gens, D, L, n, terminated, kind, pm_bits, n_streams, chunk_pbs
+    (7, (0o171, 0o133), 512, 42, 200000, True, 0, 16, 3, 0),
+    (7, (0o171, 0o133), 512, 42, 200000, True, 0, 16, 1, 64),
+    (7, (0o171, 0o133), 512, 42, 123457, False, 0, 16, 4, 8),
+    (9, (0o557, 0o663, 0o711), 256, 54, 70001, True, 0, 16, 2, 40),
+    (3, (0o7, 0o5), 100, 32, 33333, False, 1, 32, 3, 6),
+    (7, (0o133, 0o171, 0o165), 96, 42, 50000, True, 0, 16, 8, 16),
+]
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+@pytest.mark.parametrize("case", CASES, ids=[str(i) for i in range(len(CASES))])
+def test_decode_host_matches_device_decode(torch, pbvd, case, pinned):
+    K, gens, D, L, n, term, kind, pmb, ns, chunk = case
+    print("decode_host K=%d D=%d n=%d streams=%d chunk=%d pinned=%s" % (K, D, n, ns, chunk, pinned),
+          flush=True)
+    st = datagen.make_stream(K, gens, n, 2.5, seed=700 + K + D, kind=kind, terminated=term)
+    with pbvd.Plan(K, gens, D, L, term, kind, pmb) as plan:
+        ref = plan.decode(torch.from_numpy(st["syms"]).cuda(), n).cpu().numpy()
+        if pinned:
+            syms = torch.from_numpy(st["syms"]).pin_memory()
+            out = torch.zeros((n + 7) // 8, dtype=torch.uint8).pin_memory()
+            plan.decode_host(syms, n, out=out, n_streams=ns, chunk_pbs=chunk, pinned=True)
+            got = out.numpy()
+        else:
+            got = plan.decode_host(st["syms"], n, n_streams=ns, chunk_pbs=chunk)
+        # twice in a row on the same plan (buffers reused)
+        again = plan.decode_host(st["syms"], n, n_streams=ns, chunk_pbs=chunk)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(again, ref)
+    bits = np.unpackbits(got, bitorder="little")[:n]
+    sample = slice(0, min(n, 3 * D + 17))
+    ref_o = oracle.decode(K, gens, D, L, st["syms"], n, terminated=term, input_kind=kind,
+                          pb_first=0, pb_count=min(oracle.num_blocks(n, D), 4))["bits"]
+    assert np.array_equal(bits[sample], ref_o[sample])
