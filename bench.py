@@ -137,6 +137,52 @@ def plain_per_frame(torch, pbvd, codes, frames, syms, out, reps: int = 1):
     return sorted(ts)[len(ts) // 2]
 
 
+def bench_pipeline(torch, plan, st, n, kernel_mbps, reps: int = 3):
+    """Host-buffer decoding of the same stream (pinned host memory) with
+    N_s chunks on N_s streams, against the Eq. 7 estimate
+    T/P = D N_t N_s / (T_H2D + N_s T_k + T_D2H) for chunks of N_t PBs."""
+    from paper_1608_00066_amd import pbvd
+    R, D, L = plan.R, plan.D, plan.L
+    h_syms = torch.from_numpy(st["syms"]).pin_memory()
+    h_out = torch.zeros((n + 7) // 8, dtype=torch.uint8).pin_memory()
+    # PCIe rates of this box (pinned, one large copy each way)
+    d_buf = torch.empty(h_syms.numel(), dtype=torch.uint8, device="cuda")
+
+    def rate(fn, nbytes):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return nbytes * reps / (time.perf_counter() - t0)
+    b_h2d = rate(lambda: d_buf.copy_(h_syms, non_blocking=True), h_syms.numel())
+    b_d2h = rate(lambda: h_out.copy_(d_buf[:h_out.numel()], non_blocking=True), h_out.numel())
+    del d_buf
+    nb = plan.num_blocks(n)
+    res = {"h2d_GBps": round(b_h2d / 1e9, 2), "d2h_GBps": round(b_d2h / 1e9, 2), "runs": []}
+    ref = None
+    for ns in (1, 2, 3, 4, 8):
+        chunk = -(-nb // ns)
+        chunk += (-chunk) % 8
+        plan.decode_host(h_syms, n, out=h_out, n_streams=ns, chunk_pbs=chunk, pinned=True)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.decode_host(h_syms, n, out=h_out, n_streams=ns, chunk_pbs=chunk, pinned=True)
+        t = (time.perf_counter() - t0) / reps
+        if ref is None:
+            ref = h_out.clone()
+        same = bool(torch.equal(h_out, ref))
+        nt = chunk
+        t_h2d = (D + 2 * L) * nt * R / b_h2d
+        t_d2h = D * nt / 8 / b_d2h
+        t_k = D * nt / (kernel_mbps * 1e6)
+        model = D * nt * ns / (t_h2d + ns * t_k + t_d2h) / 1e6
+        res["runs"].append({"n_streams": ns, "chunk_pbs": chunk, "tp_mbps": round(n / t / 1e6, 1),
+                            "eq7_mbps": round(model, 1), "same_bits": same})
+    return res
+
+
 def bench_batched(torch, steps: int):
     """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
     50/50, Eb/N0 U[1, 5] dB): D tuned, HIP-graph replay timed, against one
@@ -306,6 +352,10 @@ def main():
                 ms2, _ = time_decode(torch, p2, syms, n, out, max(3, args.steps // 4), 2)
             sweep[str(d2)] = round(n / (ms2 * 1e-3) / 1e6, 1)
         extras["k7_r2_2p%d_mbps_by_d" % args.log2_bits] = sweep
+        log("host pipeline")
+        extras["host_pipeline"] = bench_pipeline(torch, plan, st, n, n / (kernel_ms * 1e-3) / 1e6)
+        extras["host_pipeline"]["workload"] = ("the same 2^%d-bit stream in pinned host memory, "
+                                               "N_s chunks on N_s streams" % args.log2_bits)
         log("batched decoding")
         extras["batched"] = bench_batched(torch, args.steps)
         log("serving")
