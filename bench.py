@@ -183,6 +183,27 @@ def bench_pipeline(torch, plan, st, n, kernel_mbps, reps: int = 3):
     return res
 
 
+def bench_ber_vs_l(torch, log2_bits: int = 24, ebn0s=(2.0, 3.0, 4.0),
+                   ls=(0, 7, 14, 21, 28, 35, 42, 56, 84, 210)):
+    """Bit error rate of K=7 (171,133), D=512 against the overlap L at a few
+    Eb/N0 (the experiment of Sec. V, Fig. 4, whose curve is not printed)."""
+    import numpy as np
+    from paper_1608_00066_amd import datagen, pbvd
+    n = 1 << log2_bits
+    res = {"n_bits": n, "D": 512, "by_ebn0": {}}
+    for e in ebn0s:
+        st = datagen.make_stream(7, (0o171, 0o133), n, e, datagen.config_seed(5, e, 0))
+        d_syms = torch.from_numpy(st["syms"]).cuda()
+        row = {}
+        for L in ls:
+            with pbvd.Plan(7, (0o171, 0o133), 512, L) as plan:
+                bits = np.unpackbits(plan.decode(d_syms, n).cpu().numpy(), bitorder="little")[:n]
+            row[str(L)] = float(np.mean(bits != st["info"]))
+        res["by_ebn0"][str(e)] = row
+        del d_syms
+    return res
+
+
 def bench_batched(torch, steps: int):
     """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
     50/50, Eb/N0 U[1, 5] dB): D tuned, HIP-graph replay timed, against one
@@ -356,6 +377,8 @@ def main():
         extras["host_pipeline"] = bench_pipeline(torch, plan, st, n, n / (kernel_ms * 1e-3) / 1e6)
         extras["host_pipeline"]["workload"] = ("the same 2^%d-bit stream in pinned host memory, "
                                                "N_s chunks on N_s streams" % args.log2_bits)
+        log("BER against L")
+        extras["ber_vs_L"] = bench_ber_vs_l(torch)
         log("batched decoding")
         extras["batched"] = bench_batched(torch, args.steps)
         log("serving")

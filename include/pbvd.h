@@ -87,6 +87,12 @@ typedef struct {
     int32_t input_kind; /* PBVD_SOFT_I8 or PBVD_HARD_U8 */
     int32_t pm_bits;    /* path-metric width, 16 or 32 (32 needs K <= 8);
                            results are identical, only the kernel differs */
+    int32_t lanes_per_pb; /* GPU lanes sharing one PB's trellis: 1, 2 or 4, or
+                           0 to let the library choose per call.  2 and 4 need
+                           pm_bits = 16 and K >= 7 (2) or K >= 8 (4).  More
+                           lanes per PB cut a PB's latency and let short
+                           streams fill more of the GPU; results are
+                           identical, only the kernel differs */
 } pbvd_code;
 
 /* Validate `code`, build the trellis tables and pick the kernel.

@@ -44,15 +44,16 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
         const int64_t f1 = d0 + v.D + v.L > v.T ? v.T : d0 + v.D + v.L;
         uint8_t bit = 0;
         if (d0 + row < f1) {
+            const int64_t pw = kWave >> v.lb;  // PBs per wave
             int64_t wave;
-            int lane;
+            int pbl;                            // the PB's place in its wave
             if (b >= v.b_lo && b < v.b_hi) {
-                wave = (b - v.b_lo) / kWave;
-                lane = (int)((b - v.b_lo) % kWave);
+                wave = (b - v.b_lo) / pw;
+                pbl = (int)((b - v.b_lo) % pw);
             } else {
                 const int64_t e = b < v.b_lo ? b - v.pb_first : v.n_head + (b - v.b_hi);
                 wave = v.n_int_waves + e;
-                lane = 0;
+                pbl = 0;
             }
             const int i = (int)(d0 + row - f0);       // stage index inside the PB
             const int u = rotl_dyn(state, i + 1, V);  // register map after stage i
@@ -61,15 +62,18 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
             uint32_t w;
             int pos;
             if (NR >= 16) {
+                // a row holds the PBs of the wave one after another, each
+                // PB's NR/16 dwords in register order (a lane group stores
+                // them lane by lane, which is the same order)
                 const int ndw = NR / 16;
-                w = base[((int64_t)i * kWave + lane) * ndw + (r >> 4)];
+                w = base[(int64_t)i * pw * ndw + (int64_t)pbl * ndw + (r >> 4)];
                 pos = v.byte_perm ? 16 * (r & 1) + 8 * half + ((r & 15) >> 1) : (r & 15) + 16 * half;
             } else {
                 const int S = 16 / NR;
-                w = base[(int64_t)(i / S) * kWave + lane];
+                w = base[(int64_t)(i / S) * kWave + pbl];
                 pos = (i % S) * NR + r + 16 * half;
             }
-            bit = (uint8_t)((w >> pos) & 1u);
+            bit = (uint8_t)((w >> pos) & 1);
         }
         dec[t] = bit;
     }

@@ -14,6 +14,7 @@ struct SurvivorView {
     int64_t b_lo, b_hi, n_head, n_int_waves;
     int32_t K, D, L;
     int32_t byte_perm;  // survivor bit layout: 1 = byte-permute, 0 = shift
+    int32_t lb;         // 2^lb lanes per PB (64 >> lb PBs per wave)
 };
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

@@ -16,7 +16,7 @@
 
 namespace pbvd_host {
 
-pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out) {
+pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int auto_lb) {
     if (!codes) return fail(PBVD_EINVAL, "codes must not be NULL");
     if (n < 1 || n > kMaxCodes) return fail(PBVD_EINVAL, "n_codes must be in [1, %d]", kMaxCodes);
     CodeSet cs;
@@ -29,6 +29,9 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out) {
         cs.codes[i] = codes[i];
         for (int r = codes[i].R; r < 4; ++r) cs.codes[i].gen[r] = 0;
         cs.idx[i] = idx;
+        const int req = requested_lb(codes[i]);
+        const int top = max_lb(codes[i]);
+        cs.lb[i] = req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
     }
     cs.n = n;
     *out = cs;
@@ -98,6 +101,8 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
         const pbvd_code &c = cs.codes[ci];
         const int64_t U = pbvd::trip_stages(c.K);
         const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
+        const int lb = cs.lb[ci];
+        const size_t pw = (size_t)(pbvd::kWave >> lb);  // PBs per tile
         std::vector<PbRec> &v = per_code[ci];
         // longest first (load balance); PBs that start their traceback from
         // the best state must share a tile with PBs of the same length only,
@@ -110,7 +115,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
         wl->groups[ci].tile_begin = (int64_t)wl->heads.size();
         size_t i = 0;
         while (i < v.size()) {
-            size_t e = std::min(v.size(), i + (size_t)pbvd::kWave);
+            size_t e = std::min(v.size(), i + pw);
             if (v[i].flags & pbvd::kLaneArgmin) {
                 size_t k = i + 1;
                 while (k < e && (v[k].flags & pbvd::kLaneArgmin) && v[k].len == v[i].len) ++k;
@@ -124,8 +129,9 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             h.len = 0;
             h.store0_min = 0x7fffffff;
             bool wide = true, final_needed = false;
-            for (size_t k = i; k < i + pbvd::kWave; ++k) {
-                // lanes past the tile's PBs repeat its first PB, inactive
+            for (size_t k = i; k < i + pw; ++k) {
+                // PBs past the tile's repeat its first PB, inactive; every
+                // lane of a PB's group gets the PB's descriptor
                 const PbRec &r = v[k < e ? k : i];
                 pbvd::LaneDesc d;
                 d.sym = r.sym;
@@ -134,7 +140,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 d.store0 = r.store0;
                 d.dec_end = r.dec_end;
                 d.flags = k < e ? r.flags : (r.flags & ~pbvd::kLaneActive);
-                wl->lanes.push_back(d);
+                for (int g = 0; g < (1 << lb); ++g) wl->lanes.push_back(d);
                 if (r.len > h.len) h.len = r.len;
                 if (r.store0 < h.store0_min) h.store0_min = r.store0;
                 const int64_t last_trip = ((r.len - 1) / U) * U;
@@ -146,7 +152,8 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             i = e;
         }
         wl->groups[ci].n_tiles = (int64_t)wl->heads.size() - wl->groups[ci].tile_begin;
-        wl->groups[ci].sp_wave_dwords = slot_dwords(c);
+        wl->groups[ci].sp_wave_dwords = slot_dwords(c, lb);
+        wl->groups[ci].lb = lb;
     }
     return PBVD_OK;
 }
@@ -170,6 +177,7 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
         a.n_tiles = std::min(per_launch, g.n_tiles - t0);
         req.pm_bits = cs.codes[ci].pm_bits;
         req.input_kind = cs.codes[ci].input_kind;
+        req.lb = g.lb;
         req.grid = (unsigned)ceil_div(a.n_tiles, waves_per_block);
         req.stream = stream;
         hipError_t e = launch_tiles(cs.idx[ci], req);
@@ -242,10 +250,22 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     if (!b) return fail(PBVD_EINVAL, "batch is NULL");
     if (n_frames < 0 || (n_frames > 0 && !frames)) return fail(PBVD_EINVAL, "bad frame array");
     if (sym_bytes < 0 || out_bytes < 0) return fail(PBVD_EINVAL, "negative buffer size");
+    // codes that leave the lanes per PB open: one lane per PB when the code's
+    // PBs give every SIMD a wave, the largest lane group otherwise
+    CodeSet cs = b->cs;
+    {
+        int64_t pbs[kMaxCodes] = {};
+        for (int64_t f = 0; f < n_frames; ++f)
+            if (frames[f].code >= 0 && frames[f].code < cs.n && frames[f].n_bits > 0)
+                pbs[frames[f].code] += ceil_div(frames[f].n_bits, cs.codes[frames[f].code].D);
+        for (int ci = 0; ci < cs.n; ++ci)
+            if (requested_lb(cs.codes[ci]) < 0)
+                cs.lb[ci] = ceil_div(pbs[ci], pbvd::kWave) >= 1024 ? 0 : max_lb(cs.codes[ci]);
+    }
     WorkList wl;
     pbvd_status st;
     try {
-        st = build_work_list(b->cs, frames, n_frames, sym_bytes, out_bytes, &wl);
+        st = build_work_list(cs, frames, n_frames, sym_bytes, out_bytes, &wl);
     } catch (...) {
         st = fail(PBVD_ENOMEM, "host allocation failed while building the work list");
     }
@@ -293,6 +313,7 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail_hip(e, "work-list upload");
     }
+    b->cs = cs;
     for (int ci = 0; ci < b->cs.n; ++ci) {
         b->groups[ci] = wl.groups[ci];
         b->per_launch[ci] = per_launch[ci];

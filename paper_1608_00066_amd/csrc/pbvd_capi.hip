@@ -99,10 +99,21 @@ pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char 
 }
 
 // Survivor dwords of one wave slot: every forward stage of a PB (at most
-// D + 2L) is stored, one row per stage (or per few stages for small trellises).
-int64_t slot_dwords(const pbvd_code &c) {
+// D + 2L) is stored, one row per stage (or per few stages for small
+// trellises); a row holds 64 >> lb PBs.
+int64_t slot_dwords(const pbvd_code &c, int lb) {
     const int64_t rows = ceil_div((int64_t)c.D + 2 * (int64_t)c.L, pbvd::survivor_row_stages(c.K)) + 1;
-    return ceil_div(rows * pbvd::kWave * pbvd::survivor_row_dwords(c.K), 64) * 64;
+    return ceil_div(rows * (pbvd::kWave >> lb) * pbvd::survivor_row_dwords(c.K), 64) * 64;
+}
+
+int requested_lb(const pbvd_code &c) {
+    return c.lanes_per_pb == 4 ? 2 : c.lanes_per_pb == 2 ? 1 : c.lanes_per_pb == 1 ? 0 : -1;
+}
+
+int max_lb(const pbvd_code &c) {
+    int lb = 0;
+    while (lb < 2 && pbvd::lanes_allowed(c.K, c.pm_bits, lb + 1)) ++lb;
+    return lb;
 }
 
 int64_t workspace_budget_bytes() {
@@ -133,6 +144,11 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
         return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
     if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
     if (c.pm_bits == 32 && c.K > 8) return fail(PBVD_ENOTSUP, "32-bit path metrics need K <= 8");
+    if (c.lanes_per_pb != 0 && c.lanes_per_pb != 1 && c.lanes_per_pb != 2 && c.lanes_per_pb != 4)
+        return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2 or 4 (got %d)", c.lanes_per_pb);
+    if (c.lanes_per_pb > 1 && !pbvd::lanes_allowed(c.K, c.pm_bits, requested_lb(c)))
+        return fail(PBVD_ENOTSUP, "%d lanes per PB need 16-bit metrics and K >= %d", c.lanes_per_pb,
+                    c.lanes_per_pb == 2 ? 7 : 8);
     {
         // survivor rows of one wave slot are addressed with 32-bit offsets
         const int64_t row_bytes = 64LL * pbvd::survivor_row_dwords(c.K) * 4;
@@ -168,7 +184,7 @@ struct CallGeometry {
     int64_t out_bits;
 };
 
-CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int64_t pb_count) {
+CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int64_t pb_count, int lb) {
     CallGeometry g{};
     const int64_t D = c.D, L = c.L;
     g.T = n + (c.terminated ? c.K - 1 : 0);
@@ -188,7 +204,7 @@ CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int6
         g.b_hi = hi;
         g.n_head = lo - pb_first;
         g.n_tail = g.pb_end - hi;
-        g.n_int_waves = ceil_div(hi - lo, pbvd::kWave);
+        g.n_int_waves = ceil_div(hi - lo, pbvd::kWave >> lb);
     } else {
         g.b_lo = g.b_hi = g.pb_end;
         g.n_head = pb_count;
@@ -244,7 +260,6 @@ struct pbvd_plan {
     int device;
     int ndw;                  // survivor dwords per stored row
     int row_stages;           // stages per stored row
-    int64_t sp_wave_dwords;   // survivor dwords per wave slot
     int64_t budget_bytes;     // survivor workspace limit
     Workspace ws;             // pbvd_decode / pbvd_decode_ex
     PipeStream pipe[kMaxPipeStreams];
@@ -252,9 +267,18 @@ struct pbvd_plan {
 
 namespace {
 
-int64_t waves_per_launch(const pbvd_plan *p) {
-    int64_t w = p->budget_bytes / (p->sp_wave_dwords * 4);
+int64_t waves_per_launch(const pbvd_plan *p, int64_t sp_wave_dwords) {
+    int64_t w = p->budget_bytes / (sp_wave_dwords * 4);
     return w < 1 ? 1 : w;
+}
+
+// Lanes per PB of one call: the code's choice, or else one lane per PB when
+// that already gives every SIMD a wave, the largest group otherwise.
+int call_lb(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
+    const int req = requested_lb(p->code);
+    if (req >= 0) return req;
+    const CallGeometry g0 = call_geometry(p->code, n_bits, pb_first, pb_count, 0);
+    return g0.n_waves >= 1024 ? 0 : max_lb(p->code);
 }
 
 pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
@@ -273,12 +297,16 @@ pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits
 // Runs the decode kernels of one call; fills *geo with the decomposition.
 pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
                        int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
-                       hipStream_t stream, CallGeometry *geo_out, bool single_launch) {
+                       hipStream_t stream, CallGeometry *geo_out, bool single_launch,
+                       int *lb_out = nullptr) {
     const pbvd_code &c = p->code;
-    const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count);
+    const int lb = call_lb(p, n_bits, pb_first, pb_count);
+    const int64_t sp_wave_dwords = slot_dwords(c, lb);
+    const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count, lb);
     if (geo_out) *geo_out = g;
+    if (lb_out) *lb_out = lb;
     if (pb_count == 0) return PBVD_OK;
-    const int64_t per_launch = waves_per_launch(p);
+    const int64_t per_launch = waves_per_launch(p, sp_wave_dwords);
     if (single_launch && g.n_waves > per_launch)
         return fail(PBVD_EINVAL, "%lld waves do not fit one launch (limit %lld)",
                     (long long)g.n_waves, (long long)per_launch);
@@ -286,7 +314,7 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
 
     const int64_t launch_waves = g.n_waves < per_launch ? g.n_waves : per_launch;
     pbvd_status st = ensure_buffer(&ws.sp, &ws.sp_bytes,
-                                   (size_t)(launch_waves * p->sp_wave_dwords * 4), "survivors");
+                                   (size_t)(launch_waves * sp_wave_dwords * 4), "survivors");
     if (st != PBVD_OK) return st;
 
     const int64_t out_bytes = ceil_div(g.out_bits, 8);
@@ -314,13 +342,14 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
     a.n_head = g.n_head;
     a.n_int_waves = g.n_int_waves;
     a.out_bytes = out_bytes;
-    a.sp_wave_dwords = p->sp_wave_dwords;
+    a.sp_wave_dwords = sp_wave_dwords;
     a.D = c.D;
     a.L = c.L;
     a.terminated = c.terminated;
     a.direct_out = direct ? 1 : 0;
     req.pm_bits = c.pm_bits;
     req.input_kind = c.input_kind;
+    req.lb = lb;
     req.stream = stream;
     const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
     for (int64_t w0 = 0; w0 < g.n_waves; w0 += launch_waves) {
@@ -357,7 +386,6 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
     (void)hipGetLastError();
     p->ndw = pbvd::survivor_row_dwords(c.K);
     p->row_stages = pbvd::survivor_row_stages(c.K);
-    p->sp_wave_dwords = slot_dwords(c);
     p->budget_bytes = workspace_budget_bytes();
     *out = p;
     return PBVD_OK;
@@ -421,11 +449,13 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
     hipStream_t s = (hipStream_t)hip_stream;
     CallGeometry g{};
-    st = run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true);
+    int lb = 0;
+    st = run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true, &lb);
     if (st != PBVD_OK || pb_count == 0) return st;
     pbvd::SurvivorView v{};
     v.sp = p->ws.sp;
-    v.sp_wave_dwords = p->sp_wave_dwords;
+    v.sp_wave_dwords = slot_dwords(p->code, lb);
+    v.lb = lb;
     v.T = g.T;
     v.pb_first = pb_first;
     v.pb_count = pb_count;

@@ -19,11 +19,46 @@ struct CodeAt;
 PBVD_CODE_LIST(PBVD_CODE_AT)
 #undef PBVD_CODE_AT
 
+template <class C, class P, int KIND, int LB>
+hipError_t launch_lb(const LaunchRequest &req) {
+    if constexpr (lanes_supported<C, P, LB>()) {
+        hipLaunchKernelGGL((decode_kernel<C, P, KIND, LB>), dim3(req.grid), dim3(kBlockThreads), 0,
+                           req.stream, req.args);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
 template <class C, class P, int KIND>
 hipError_t launch_one(const LaunchRequest &req) {
-    hipLaunchKernelGGL((decode_kernel<C, P, KIND>), dim3(req.grid), dim3(kBlockThreads), 0,
-                       req.stream, req.args);
-    return hipGetLastError();
+    switch (req.lb) {
+    case 0: return launch_lb<C, P, KIND, 0>(req);
+    case 1: return launch_lb<C, P, KIND, 1>(req);
+    case 2: return launch_lb<C, P, KIND, 2>(req);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class C, class P, int KIND, int LB>
+hipError_t launch_tiles_lb(const TileLaunchRequest &req) {
+    if constexpr (lanes_supported<C, P, LB>()) {
+        hipLaunchKernelGGL((decode_tiles_kernel<C, P, KIND, LB>), dim3(req.grid), dim3(kBlockThreads), 0,
+                           req.stream, req.args);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <class C, class P, int KIND>
+hipError_t launch_tiles_one(const TileLaunchRequest &req) {
+    switch (req.lb) {
+    case 0: return launch_tiles_lb<C, P, KIND, 0>(req);
+    case 1: return launch_tiles_lb<C, P, KIND, 1>(req);
+    case 2: return launch_tiles_lb<C, P, KIND, 2>(req);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -41,13 +76,6 @@ hipError_t launch_code(const LaunchRequest &req) {
                                              : launch_one<C, PM32, kSoftI8>(req);
     }
     return hipErrorInvalidValue;
-}
-
-template <class C, class P, int KIND>
-static hipError_t launch_tiles_one(const TileLaunchRequest &req) {
-    hipLaunchKernelGGL((decode_tiles_kernel<C, P, KIND>), dim3(req.grid), dim3(kBlockThreads), 0,
-                       req.stream, req.args);
-    return hipGetLastError();
 }
 
 template <int IDX>

@@ -38,8 +38,14 @@ pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char 
 // Validates a code/block parameter set; *idx_out receives its registry index.
 pbvd_status check_code(const pbvd_code &c, int *idx_out);
 
-// Survivor dwords of one wave slot of a code (all D + 2L forward rows).
-int64_t slot_dwords(const pbvd_code &c);
+// Survivor dwords of one wave slot of a code (all D + 2L forward rows) with
+// 2^lb lanes per PB.
+int64_t slot_dwords(const pbvd_code &c, int lb);
+
+// log2 of the lanes per PB a code asks for (-1: the library chooses).
+int requested_lb(const pbvd_code &c);
+// The largest lane group a code supports.
+int max_lb(const pbvd_code &c);
 
 // Survivor workspace limit of one plan or batch (PBVD_WORKSPACE_MB, default 8 GiB).
 int64_t workspace_budget_bytes();
@@ -55,14 +61,18 @@ struct CodeSet {
     int n = 0;
     pbvd_code codes[kMaxCodes];
     int idx[kMaxCodes];
+    int lb[kMaxCodes];   // lanes per PB used for each code (log2)
 };
 
-// Validates n codes for batched use (D % 8 == 0) into *out.
-pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out);
+// Validates n codes for batched use (D % 8 == 0) into *out.  Codes that let
+// the library choose their lanes per PB get auto_lb (clipped to what the
+// code supports; -1: the largest it supports).
+pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int auto_lb = 0);
 
 struct TileGroup {
     int64_t tile_begin = 0, n_tiles = 0;
     int64_t sp_wave_dwords = 0;
+    int lb = 0;
 };
 
 // Tiles (waves of 64 PBs) of a set of frames, grouped by code.

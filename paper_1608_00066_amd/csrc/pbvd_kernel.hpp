@@ -63,7 +63,7 @@ struct KernelArgs {
     int64_t pb_first;       // first PB of this call
     int64_t b_lo, b_hi;     // interior PBs (full geometry) of this call
     int64_t n_head;         // edge PBs [pb_first, pb_first + n_head) precede b_lo
-    int64_t n_int_waves;    // waves covering [b_lo, b_hi), 64 PBs each
+    int64_t n_int_waves;    // waves covering [b_lo, b_hi), 64 >> LB PBs each
     int64_t wave_begin;     // first wave (interior waves first, then edge waves)
     int64_t n_waves;        // waves in this launch
     int64_t out_bytes;      // bytes of `out`
@@ -133,6 +133,12 @@ __device__ __forceinline__ uint32_t u_to_idx(uint32_t u) {
 
 // ---------------------------------------------------------------------------
 // Packed path-metric pairs
+// Value of v in another lane of the same quad (DPP quad_perm control CTRL).
+template <int CTRL>
+__device__ __forceinline__ int dpp_int(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, false);
+}
+
 // ---------------------------------------------------------------------------
 struct PM16 {
     typedef short v2 __attribute__((ext_vector_type(2)));
@@ -161,6 +167,10 @@ struct PM16 {
     }
     static __device__ __forceinline__ int lo(T a) { return a.x; }
     static __device__ __forceinline__ int hi(T a) { return a.y; }
+    template <int CTRL>
+    static __device__ __forceinline__ T dpp(T a) {
+        return __builtin_bit_cast(T, dpp_int<CTRL>(__builtin_bit_cast(int, a)));
+    }
 };
 
 struct PM32 {
@@ -177,6 +187,8 @@ struct PM32 {
     }
     static __device__ __forceinline__ int lo(T a) { return a.x; }
     static __device__ __forceinline__ int hi(T a) { return a.y; }
+    template <int CTRL>
+    static __device__ __forceinline__ T dpp(T a) { return T{dpp_int<CTRL>(a.x), dpp_int<CTRL>(a.y)}; }
 };
 
 // acc | (x << SH) as one v_lshl_or_b32.  Written out so that the compiler
@@ -203,11 +215,13 @@ typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
 
-template <int NDW>
+// A lane moves NDW dwords of a row; consecutive rows are ROW_DW dwords apart
+// (64 lanes x their own dwords when every lane stores its part).
+template <int NDW, int ROW_DW = kWave * NDW>
 struct RowStore {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t lane_off;  // bytes
-    static constexpr int kRowBytes = kWave * NDW * 4;
+    static constexpr int kRowBytes = ROW_DW * 4;
     __device__ __forceinline__ void store(int row, const uint32_t (&v)[NDW]) const {
         const int so = row * kRowBytes;
         if constexpr (NDW == 1) {
@@ -255,10 +269,10 @@ __device__ __forceinline__ int rx_value(const uint8_t *p) {
 // of q_r.  The Sec. II distance sum_r [c^(r) != (q_r < 0)] |q_r| equals this
 // plus sum_r max(-q_r, 0), which is the same for every c.
 template <int R>
-__device__ __forceinline__ void code_word_metrics(const int (&q)[R], int (&bm)[1 << R]) {
+__device__ __forceinline__ void code_word_metrics(const int (&q)[R], int (&bm)[1 << R], int base = 0) {
 #pragma unroll
     for (int c = 0; c < (1 << R); ++c) {
-        int s = 0;
+        int s = base;
 #pragma unroll
         for (int r = 0; r < R; ++r)
             if ((c >> (R - 1 - r)) & 1) s += q[r];
@@ -267,19 +281,34 @@ __device__ __forceinline__ void code_word_metrics(const int (&q)[R], int (&bm)[1
 }
 
 // ---------------------------------------------------------------------------
-// One trellis stage at compile-time phase PH.  Writes the stage's decision
-// bits into dw[] at slot offset SLOT0 (in units of packed registers) in the
-// shift layout, or in the byte-permute layout when BP.
+// Lanes per PB.  With 2^LB lanes per PB (LB = 1 or 2) the registers of a PB
+// are spread over a group of consecutive lanes: lane l of the group holds the
+// states whose register index has l in its top LB bits.  Stages whose
+// butterfly pairs registers of different lanes read the partner's metrics
+// with a DPP quad permute; every lane keeps its own half of each pair.
 // ---------------------------------------------------------------------------
-template <class C, class P, int PH, int SLOT0, int NDW, bool BP>
-__device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int (&q)[C::R],
+__host__ __device__ constexpr int quad_sel(int a, int b, int c, int d) { return a | (b << 2) | (c << 4) | (d << 6); }
+// quad-permute controls: read the lane of the group with lane bit B cleared /
+// set, flip lane bit 0 / 1, or read the group's first lane
+template <int B> __host__ __device__ constexpr int quad_lo() { return B == 0 ? quad_sel(0, 0, 2, 2) : quad_sel(0, 1, 0, 1); }
+template <int B> __host__ __device__ constexpr int quad_hi() { return B == 0 ? quad_sel(1, 1, 3, 3) : quad_sel(2, 3, 2, 3); }
+template <int B> __host__ __device__ constexpr int quad_flip() { return B == 0 ? quad_sel(1, 0, 3, 2) : quad_sel(2, 3, 0, 1); }
+template <int LB> __host__ __device__ constexpr int quad_first() { return LB == 1 ? quad_sel(0, 0, 2, 2) : quad_sel(0, 0, 0, 0); }
+
+// ---------------------------------------------------------------------------
+// One trellis stage at compile-time phase PH on the NR >> LB registers of a
+// lane, with the stage's branch metrics bm[] already relabeled for the lane
+// (see lane_code_mask).  Writes the stage's decision bits into dw[] at slot
+// offset SLOT0 (in units of packed registers) in the shift layout, or in the
+// byte-permute layout when BP.
+// ---------------------------------------------------------------------------
+template <class C, class P, int PH, int SLOT0, int NDW, bool BP, int LB>
+__device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR >> LB], const int (&bm)[C::NC],
                                           uint32_t (&dw)[NDW]) {
     using T = typename P::T;
-    constexpr int V = C::V, NR = C::NR, NC = C::NC;
+    constexpr int V = C::V, NR = C::NR >> LB, NC = C::NC;
     constexpr int G0 = C::gcol(0), GK = C::gcol(C::K - 1);
-
-    int bm[NC];
-    code_word_metrics<C::R>(q, bm);
+    constexpr int kCross = V - 1 - LB;  // first phase whose pair bit is a lane bit
 
     // decisions of register X (two per register: lower and upper half)
     uint32_t dd[NR];
@@ -302,8 +331,8 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
         }
     };
 
-    if constexpr (PH < V - 1) {
-        // pairs (X, Y = X | 2^PH); halves differ in state bit V-1-PH
+    if constexpr (PH < kCross) {
+        // pairs (X, Y = X | 2^PH) inside the lane; halves differ in state bit V-1-PH
         constexpr int GP = C::gcol(V - 1 - PH);
         T pair[NC];
 #pragma unroll
@@ -323,6 +352,27 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
             record(std::integral_constant<int, Y>{}, a1, b1);
             return true;
         });
+    } else if constexpr (PH < V - 1) {
+        // the pair bit is lane bit B: register X of the group's lane with B
+        // clear holds S_2j, the same register of the lane with B set holds
+        // S_2j+1; each lane computes the new metrics it keeps (input 0 for B
+        // clear, input 1 for B set, folded into its relabeled metrics)
+        constexpr int B = PH - kCross;
+        constexpr int GP = C::gcol(V - 1 - PH);
+        T pair[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) pair[c] = P::make(bm[c], bm[c ^ GP]);
+        static_for<0, NR>([&](auto xc) PBVD_INLINE_LAMBDA {
+            constexpr int X = decltype(xc)::value;
+            constexpr int alpha = C::out0(rotr_v<V>(X, PH));
+            const T xv = P::template dpp<quad_lo<B>()>(pm[X]);
+            const T yv = P::template dpp<quad_hi<B>()>(pm[X]);
+            const T a = P::add(xv, pair[alpha]);
+            const T b = P::add(yv, pair[alpha ^ G0]);
+            pm[X] = P::vmin(a, b);
+            record(xc, a, b);
+            return true;
+        });
     } else {
         // each register holds (S_2j, S_2j+1): broadcast operands
         T pair[NC];
@@ -340,13 +390,38 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR], const int 
     }
 }
 
+// Relabeling of the code words for lane bit j at phase PH.  The code word of
+// a branch is linear (over GF(2)) in the state bits, so the lane bits add the
+// same mask to every branch of a lane: the lane uses metric[c ^ mask] where
+// the stage code above uses metric[c].  In a stage whose pair bit is lane
+// bit j, the lane with that bit set computes the input-1 outputs, whose code
+// words differ by g_{K-1} (Eq. 4, Eq. 6).
+template <class C, int LB>
+__host__ __device__ constexpr int lane_code_mask(int PH, int j) {
+    constexpr int V = C::V;
+    const int kCross = V - 1 - LB;
+    if (PH >= kCross && PH < V - 1 && PH - kCross == j) return C::gcol(C::K - 1);
+    return C::out0(rotr_v<V>(1 << (kCross + j), PH));
+}
+// masks of all phases packed R bits per phase (phase PH at bit R*PH)
+template <class C, int LB>
+__host__ __device__ constexpr uint32_t lane_code_mask_pack(int j) {
+    uint32_t m = 0;
+    for (int ph = 0; ph < C::V; ++ph) m |= (uint32_t)lane_code_mask<C, LB>(ph, j) << (C::R * ph);
+    return m;
+}
+
 // ---------------------------------------------------------------------------
 // Compile-time layout constants of one code
 // ---------------------------------------------------------------------------
-template <class C, class P>
+template <class C, class P, int LB = 0>
 struct Layout {
-    static constexpr int V = C::V, NR = C::NR;
-    static constexpr int NDW = NR >= 16 ? NR / 16 : 1;   // survivor dwords per stored row
+    static constexpr int V = C::V;
+    static constexpr int NR = C::NR >> LB;                // packed registers per lane
+    static constexpr int GL = 1 << LB;                    // lanes per PB
+    static constexpr int PW = kWave >> LB;                // PBs per wave
+    static constexpr int NDW = NR >= 16 ? NR / 16 : 1;    // survivor dwords a lane stores per row
+    static constexpr int NDW_F = NDW * GL;                // survivor dwords of one PB's row
     static constexpr int S = NR >= 16 ? 1 : 16 / NR;      // stages per stored row
     static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
     static constexpr int U = V / gcd(V, S) * S;           // unrolled stages per loop trip
@@ -361,7 +436,17 @@ struct Layout {
     static constexpr int kRenormTrips =
         kMaxStages / U > (1 << 30) ? (1 << 30) : (int)(kMaxStages / U);
     static_assert(kRenormTrips >= 1, "metric range too small for this code");
+    // a lane group must fill whole survivor dwords with the byte-permute
+    // layout, so that a PB's row is the same bits as with one lane per PB
+    static_assert(LB == 0 || (LB <= 2 && NR >= 16 && std::is_same<P, PM16>::value),
+                  "lane groups need 16-bit metrics and at least 16 registers per lane");
 };
+
+// Lane groups a code supports (compile-time mirror of lanes_allowed on the host).
+template <class C, class P, int LB>
+__host__ __device__ constexpr bool lanes_supported() {
+    return LB == 0 || (LB <= 2 && (C::NR >> LB) >= 16 && std::is_same<P, PM16>::value);
+}
 
 template <int V>
 __device__ __forceinline__ int rotr_rt(int u, int s) {
@@ -401,23 +486,54 @@ struct WaveJob {
 // start at stage 0 with their own initial metrics; a lane's stages past its
 // own end compute values nobody reads, and its traceback starts at its own
 // last stage.
-template <class C, class P, int KIND, bool VARLEN>
-__device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Layout<C, P>::NDW> &rows) {
+template <class C, class P, int KIND, bool VARLEN, int LB>
+__device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Layout<C, P, LB>::NDW> &rows) {
     using T = typename P::T;
-    using LY = Layout<C, P>;
-    constexpr int V = C::V, N = C::N, NR = C::NR, R = C::R;
-    constexpr int NDW = LY::NDW, S = LY::S, U = LY::U;
+    using LY = Layout<C, P, LB>;
+    constexpr int V = C::V, N = C::N, NR = LY::NR, R = C::R, NC = C::NC;
+    constexpr int NDW = LY::NDW, NDW_F = LY::NDW_F, S = LY::S, U = LY::U;
     const int len = j.len;
     const uint8_t *const in = j.in;
+    // lane within the PB's group; its bits are the top register-index bits
+    const int ell = LB ? (int)(threadIdx.x & ((1u << LB) - 1)) : 0;
 
     // ---- initial metrics ----
     T pm[NR];
     {
         // known start state 0 when the lane's forward range starts at stage 0
         const int big = j.known ? 8192 : 0;
+        const int zero = ell == 0 ? 0 : big;
 #pragma unroll
-        for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? 0 : big, big);
+        for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? zero : big, big);
     }
+    // code-word relabel masks of this lane, R bits per phase
+    uint32_t lane_masks = 0;
+    if constexpr (LB >= 1) lane_masks ^= (ell & 1) ? lane_code_mask_pack<C, LB>(0) : 0u;
+    if constexpr (LB >= 2) lane_masks ^= (ell & 2) ? lane_code_mask_pack<C, LB>(1) : 0u;
+    // branch metrics of stage phase PH for this lane: metric[c ^ mask]
+    auto stage_metrics = [&](auto phc, int (&q)[R], int (&bm)[NC]) PBVD_INLINE_LAMBDA {
+        constexpr int PH = decltype(phc)::value;
+        if constexpr (LB == 0) {
+            code_word_metrics<R>(q, bm);
+        } else {
+            int base = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if ((lane_masks >> (R * PH + R - 1 - r)) & 1u) {
+                    base += q[r];
+                    q[r] = -q[r];
+                }
+            }
+            code_word_metrics<R>(q, bm, base);
+        }
+    };
+    // renormalization reference: the group's first lane's metric of register 0
+    auto renorm = [&]() PBVD_INLINE_LAMBDA {
+        T ref = P::bcast_lo(pm[0]);
+        if constexpr (LB > 0) ref = P::template dpp<quad_first<LB>()>(ref);
+#pragma unroll
+        for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
+    };
 
     // ---- forward procedure ----
     // Received symbols of one loop trip (U stages, NB bytes) are fetched with
@@ -497,15 +613,14 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
             fetch(raw_next, sh_next, i0 + U, true);
             if (++trips_since_renorm == LY::kRenormTrips) {
                 trips_since_renorm = 0;
-                const T ref = P::bcast_lo(pm[0]);
-#pragma unroll
-                for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
+                renorm();
             }
             static_for<0, U>([&](auto kc) PBVD_INLINE_LAMBDA {
                 constexpr int k = decltype(kc)::value;
-                int q[R];
+                int q[R], bm[NC];
                 symbols(wsym, k, q);
-                acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm>(pm, q, dw);
+                stage_metrics(std::integral_constant<int, k % V>{}, q, bm);
+                acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm, LB>(pm, bm, dw);
                 if constexpr ((k % S) == S - 1) {
                     rows.store((i0 + k) / S, dw);
 #pragma unroll
@@ -521,16 +636,15 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         if (!last_trip) fetch(raw_next, sh_next, i0 + U, j.fetch_safe);
         if (++trips_since_renorm == LY::kRenormTrips) {
             trips_since_renorm = 0;
-            const T ref = P::bcast_lo(pm[0]);
-#pragma unroll
-            for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
+            renorm();
         }
         const bool more = static_for<0, U>([&](auto kc) PBVD_INLINE_LAMBDA {
             constexpr int k = decltype(kc)::value;
             if (i0 + k >= len) return false;
-            int q[R];
+            int q[R], bm[NC];
             symbols(wsym, k, q);
-            acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm>(pm, q, dw);
+            stage_metrics(std::integral_constant<int, k % V>{}, q, bm);
+            acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm, LB>(pm, bm, dw);
             if ((k % S) == S - 1 || i0 + k + 1 == len) {
                 rows.store((i0 + k) / S, dw);
 #pragma unroll
@@ -547,28 +661,36 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     const int ph_end = len % V;
     uint32_t idx = 0;  // rotated index of state 0 is 0
     if (j.need_final) {
+        // rotated index of this lane's register r: u = r | ell << (K-2-LB),
+        // plus 2^(K-2) for the upper half
+        const int ubase = ell << (V - 1 - LB);
         int m = 0x7fffffff;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             m = min(m, P::lo(pm[r]));
             m = min(m, P::hi(pm[r]));
         }
+        if constexpr (LB >= 1) m = min(m, dpp_int<quad_flip<0>()>(m));
+        if constexpr (LB >= 2) m = min(m, dpp_int<quad_flip<1>()>(m));
         if (j.argmin) {
             int best = N;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                const int s_lo = rotr_rt<V>(r, ph_end), s_hi = rotr_rt<V>(r + NR, ph_end);
+                const int s_lo = rotr_rt<V>(ubase | r, ph_end);
+                const int s_hi = rotr_rt<V>(ubase | r | (1 << (V - 1)), ph_end);
                 if (P::lo(pm[r]) == m && s_lo < best) best = s_lo;
                 if (P::hi(pm[r]) == m && s_hi < best) best = s_hi;
             }
+            if constexpr (LB >= 1) best = min(best, dpp_int<quad_flip<0>()>(best));
+            if constexpr (LB >= 2) best = min(best, dpp_int<quad_flip<1>()>(best));
             idx = u_to_idx<V, LY::kBytePerm>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
         }
         if (j.pm_out && j.active) {
             int32_t *fp = j.pm_out;
 #pragma unroll
             for (int r = 0; r < NR; ++r) {
-                fp[rotr_rt<V>(r, ph_end)] = P::lo(pm[r]) - m;
-                fp[rotr_rt<V>(r + NR, ph_end)] = P::hi(pm[r]) - m;
+                fp[rotr_rt<V>(ubase | r, ph_end)] = P::lo(pm[r]) - m;
+                fp[rotr_rt<V>(ubase | r | (1 << (V - 1)), ph_end)] = P::hi(pm[r]) - m;
             }
         }
     }
@@ -577,7 +699,13 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     // The survivor rows of a PB do not depend on the state being traced, so
     // blocks of TBR rows are loaded one block ahead of their use; only the
     // bit selection inside a row follows the state.
-    constexpr int TBR = NDW >= 4 ? 4 : (NDW == 2 ? 8 : (16 / S));  // <= 16 stages, <= 32 dwords per block
+    // every lane of a group traces its PB's whole row; the group's first lane
+    // writes the bits
+    constexpr int TBR = NDW_F >= 4 ? 4 : (NDW_F == 2 ? 8 : (16 / S));  // <= 16 stages, <= 32 dwords per block
+    RowStore<NDW_F, kWave * NDW> tb_rows;
+    tb_rows.rsrc = rows.rsrc;
+    tb_rows.lane_off = LB ? (uint32_t)(threadIdx.x & (kWave - 1)) / (1u << LB) * (NDW_F * 4) : rows.lane_off;
+    const bool writer = j.active && ell == 0;
     const int i_lo = j.store0_min;
     const int row_lo = i_lo / S;
     const int row_hi = (len - 1) / S;
@@ -585,11 +713,11 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     uint32_t word = 0;
     int ph = (len - 1) % V;  // input phase of the stage being traced
 
-    auto load_block = [&](uint32_t (&dst)[TBR][NDW], int top) PBVD_INLINE_LAMBDA {
+    auto load_block = [&](uint32_t (&dst)[TBR][NDW_F], int top) PBVD_INLINE_LAMBDA {
 #pragma unroll
         for (int t = 0; t < TBR; ++t) {
             const int row = top - t < row_lo ? row_lo : top - t;
-            rows.load(row, dst[t]);
+            tb_rows.load(row, dst[t]);
         }
     };
 
@@ -620,7 +748,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     };
 
     // one traceback step at stage i with that stage's survivor row
-    auto step = [&](int i, const uint32_t (&row)[NDW], int sub) PBVD_INLINE_LAMBDA {
+    auto step = [&](int i, const uint32_t (&row)[NDW_F], int sub) PBVD_INLINE_LAMBDA {
         const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
         bool live = true;
         if constexpr (VARLEN) live = i < j.my_len && i >= j.my_store0;
@@ -630,25 +758,25 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
                 word = (word << 1) | x;
                 const int rel = i - j.my_store0;
                 if ((rel & 31) == 0) {
-                    if (j.active) put_word(rel, n_dec - rel < 32 ? n_dec - rel : 32);
+                    if (writer) put_word(rel, n_dec - rel < 32 ? n_dec - rel : 32);
                     word = 0;
                 }
             }
             uint32_t dec;
-            if constexpr (NDW == 1) {
+            if constexpr (NDW_F == 1) {
                 dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
-            } else if constexpr (NDW == 2) {
+            } else if constexpr (NDW_F == 2) {
                 const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
                 dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
             } else {
                 // select dword idx >> 5 with a binary tree, most significant
                 // index bit first (v[w + half] differs from v[w] in that bit)
-                uint32_t v[NDW];
+                uint32_t v[NDW_F];
 #pragma unroll
-                for (int w = 0; w < NDW; ++w) v[w] = row[w];
-                constexpr int kTopBit = 4 + (NDW >= 8 ? 3 : NDW >= 4 ? 2 : 1);
+                for (int w = 0; w < NDW_F; ++w) v[w] = row[w];
+                constexpr int kTopBit = 4 + (NDW_F >= 8 ? 3 : NDW_F >= 4 ? 2 : 1);
 #pragma unroll
-                for (int half = NDW / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
+                for (int half = NDW_F / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
                     const bool up = (idx >> bit) & 1u;
 #pragma unroll
                     for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
@@ -661,7 +789,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     };
 
     // trace rows top..top-TBR+1; false once the first traced stage is passed
-    auto run_block = [&](const uint32_t (&blk)[TBR][NDW], int top) PBVD_INLINE_LAMBDA {
+    auto run_block = [&](const uint32_t (&blk)[TBR][NDW_F], int top) PBVD_INLINE_LAMBDA {
         return static_for<0, TBR>([&](auto tc) PBVD_INLINE_LAMBDA {
             constexpr int t = decltype(tc)::value;
             const int row = top - t;
@@ -677,7 +805,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         });
     };
 
-    uint32_t ra[TBR][NDW], rb[TBR][NDW];
+    uint32_t ra[TBR][NDW_F], rb[TBR][NDW_F];
     int top = row_hi;
     load_block(ra, top);
     for (;;) {
@@ -702,15 +830,16 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
 // Stream kernel: the PBs of one stream (Sec. III-A, Fig. 2).  Interior PBs
 // (full geometry) go 64 to a wave; PBs at the stream ends get a wave each.
 // ---------------------------------------------------------------------------
-template <class C, class P, int KIND>
+template <class C, class P, int KIND, int LB>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    __attribute__((amdgpu_waves_per_eu((C::NR >> LB) >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
     decode_kernel(const KernelArgs a) {
-    using LY = Layout<C, P>;
-    constexpr int R = C::R, N = C::N;
+    using LY = Layout<C, P, LB>;
+    constexpr int R = C::R, N = C::N, PW = LY::PW;
     constexpr int ND = (LY::U * R + 3) / 4 + 1;
 
     const int lane = threadIdx.x & (kWave - 1);
+    const int pl = lane >> LB;  // the lane's PB inside the wave
     // wave index made provably uniform so that all geometry stays scalar
     const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
                                __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -724,12 +853,12 @@ __global__ void __launch_bounds__(256)
     int64_t lane_stage_off;           // this lane's stage offset from f0w
     int64_t far_lane;                 // the wave's last real lane
     if (wave < a.n_int_waves) {
-        const int64_t bw = a.b_lo + wave * kWave;
-        b = bw + lane;
+        const int64_t bw = a.b_lo + wave * PW;
+        b = bw + pl;
         active = b < a.b_hi;
-        lane_stage_off = (active ? (int64_t)lane : (a.b_hi - 1 - bw)) * D;
+        lane_stage_off = (active ? (int64_t)pl : (a.b_hi - 1 - bw)) * D;
         if (!active) b = a.b_hi - 1;
-        far_lane = a.b_hi - 1 - bw < kWave - 1 ? a.b_hi - 1 - bw : kWave - 1;
+        far_lane = a.b_hi - 1 - bw < PW - 1 ? a.b_hi - 1 - bw : PW - 1;
         d0w = bw * D;
         f0w = d0w - L;
         f1w = d0w + D + L;
@@ -737,7 +866,7 @@ __global__ void __launch_bounds__(256)
     } else {
         const int64_t e = wave - a.n_int_waves;
         b = e < a.n_head ? a.pb_first + e : a.b_hi + (e - a.n_head);
-        active = lane == 0;
+        active = pl == 0;
         lane_stage_off = 0;
         far_lane = 0;
         d0w = b * D;
@@ -775,12 +904,13 @@ __global__ void __launch_bounds__(256)
     rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
                                                   (int)(a.sp_wave_dwords * 4), kBufferFlags);
     rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
-    decode_body<C, P, KIND, false>(j, rows);
+    decode_body<C, P, KIND, false, LB>(j, rows);
 }
 
 // ---------------------------------------------------------------------------
-// Batch kernel: one wave per tile of up to 64 PBs of one code taken from any
-// frames (lengths may differ inside a tile).
+// Batch kernel: one wave per tile of up to 64 >> LB PBs of one code taken
+// from any frames (lengths may differ inside a tile).  With lane groups the
+// descriptor of a PB is repeated for each lane of its group.
 // ---------------------------------------------------------------------------
 struct LaneDesc {
     int64_t sym;       // byte offset in syms of the PB's first forward stage
@@ -811,11 +941,11 @@ struct TileArgs {
     int64_t n_tiles;
 };
 
-template <class C, class P, int KIND>
+template <class C, class P, int KIND, int LB>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(C::NR >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    __attribute__((amdgpu_waves_per_eu((C::NR >> LB) >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
     decode_tiles_kernel(const TileArgs a) {
-    using LY = Layout<C, P>;
+    using LY = Layout<C, P, LB>;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
                                __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -850,7 +980,7 @@ __global__ void __launch_bounds__(256)
     rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
                                                   (int)(a.sp_wave_dwords * 4), kBufferFlags);
     rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
-    decode_body<C, P, KIND, true>(j, rows);
+    decode_body<C, P, KIND, true, LB>(j, rows);
 }
 
 }  // namespace pbvd

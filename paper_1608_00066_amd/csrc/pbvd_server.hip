@@ -76,20 +76,23 @@ struct Footprint {
         pbs[r.code] += r.n_pbs;
         if (!cs.codes[r.code].terminated) argmin_frames[r.code] += 1;
     }
-    int64_t tiles(int ci) const { return ceil_div(pbs[ci], pbvd::kWave) + argmin_frames[ci]; }
+    // lb[] of the code set: 64 >> lb PBs per tile
+    int64_t tiles(int ci, const CodeSet &cs) const {
+        return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + argmin_frames[ci];
+    }
     int64_t lanes_bytes(const CodeSet &cs) const {
         int64_t t = 0;
-        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci);
+        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci, cs);
         return align_up(t * pbvd::kWave * (int64_t)sizeof(pbvd::LaneDesc));
     }
     int64_t heads_bytes(const CodeSet &cs) const {
         int64_t t = 0;
-        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci);
+        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci, cs);
         return align_up(t * (int64_t)sizeof(pbvd::TileHead));
     }
     int64_t sp_bytes(const CodeSet &cs) const {
         int64_t b = 0;
-        for (int ci = 0; ci < cs.n; ++ci) b += align_up(tiles(ci) * slot_dwords(cs.codes[ci]) * 4);
+        for (int ci = 0; ci < cs.n; ++ci) b += align_up(tiles(ci, cs) * slot_dwords(cs.codes[ci], cs.lb[ci]) * 4);
         return b;
     }
     int64_t in_bytes(const CodeSet &cs) const { return align_up(sym) + lanes_bytes(cs) + heads_bytes(cs); }
@@ -375,7 +378,8 @@ pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pb
     if (cfg->device_bytes < ((int64_t)cfg->max_inflight << 20))
         return fail(PBVD_EINVAL, "device_bytes must be at least 1 MiB per batch in flight");
     CodeSet cs;
-    pbvd_status st = make_code_set(codes, n_codes, &cs);
+    // latency first: codes that leave it open get the largest lane group
+    pbvd_status st = make_code_set(codes, n_codes, &cs, -1);
     if (st != PBVD_OK) return st;
     pbvd_server *sv = new (std::nothrow) pbvd_server();
     if (!sv) return fail(PBVD_ENOMEM, "host allocation failed");

@@ -158,3 +158,15 @@ def test_batch_full_size_tuned(torch, pbvd):
     for p in plans:
         p.close()
     assert torch.equal(alone, out)
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+def test_batch_lane_groups(torch, pbvd, lanes):
+    """Batches with 2^lb lanes per PB (K=7 takes at most 2): same bits as the
+    oracle and as one lane per PB."""
+    l7 = min(lanes, 2)
+    codes = [dict(K=7, gens=(0o171, 0o133), D=96, L=42, lanes_per_pb=l7),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=64, L=54, lanes_per_pb=lanes),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=128, L=54, terminated=False, lanes_per_pb=lanes)]
+    log("batch lanes %d: K=7 + K=9 + K=9 unterminated, lengths 1..3000" % lanes)
+    check_batch(torch, pbvd, codes, 90, 1, 3000, seed=41 + lanes)

@@ -50,12 +50,13 @@ def gpu_bits(torch, out, nbits):
     return np.unpackbits(out.cpu().numpy(), bitorder="little")[:nbits]
 
 
-def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=True):
+def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=True, lanes=0):
     """Decode PBs [pb_first, pb_first+pb_count) on GPU and oracle; compare
-    bits, normalized final metrics and (optionally) survivor decisions."""
+    bits, normalized final metrics and (optionally) survivor decisions.
+    lanes: lanes per PB of the plan (0: the library's choice)."""
     K, gens, n, kind = st["K"], st["gens"], st["n"], st["kind"]
     term = st["terminated"]
-    with pbvd.Plan(K, gens, D, L, term, kind, pm_bits) as plan:
+    with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes) as plan:
         dsyms = to_dev(torch, st["syms"])
         nbits = plan.out_bits(n, pb_first, pb_count)
         out, fpm = plan.decode_ex(dsyms, n, pb_first, pb_count, want_pm=True)
@@ -185,6 +186,52 @@ def test_fuzz_parity(torch, pbvd, case):
     st = datagen.make_stream(K, gens, n, ebn0, seed=5000 + i, kind=kind, terminated=term)
     nb = oracle.num_blocks(n, D)
     check_range(torch, pbvd, st, D, L, pm, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7)
+
+
+def lane_cases():
+    return [c for c in fuzz_cases() if c[1] >= 7 and c[8] == 16]
+
+
+@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("case", lane_cases(), ids=lambda c: "f%d" % c[0])
+def test_lane_groups_parity(torch, pbvd, case, lanes):
+    """Every lane-group width a code supports gives the oracle's bits, final
+    metrics and survivor decisions; unsupported widths are refused."""
+    i, K, gens, n, D, L, term, kind, pm, ebn0 = case
+    if lanes == 4 and K < 8:
+        with pytest.raises(pbvd.PbvdError) as ei:
+            pbvd.Plan(K, gens, D, L, term, kind, pm, lanes)
+        assert ei.value.status == pbvd.PBVD_ENOTSUP
+        return
+    log("lanes %d fuzz %d: K=%d R=%d n=%d D=%d L=%d term=%d kind=%d" % (lanes, i, K, len(gens), n, D, L,
+                                                                         term, kind))
+    st = datagen.make_stream(K, gens, n, ebn0, seed=5000 + i, kind=kind, terminated=term)
+    nb = oracle.num_blocks(n, D)
+    check_range(torch, pbvd, st, D, L, pm, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7,
+                lanes=lanes)
+
+
+@pytest.mark.parametrize("K,lanes", [(7, 2), (9, 2), (9, 4)])
+def test_lane_groups_full_size_sampled(torch, pbvd, c3_streams, K, lanes):
+    """The 2^27-bit streams at D=512 with lane groups: sampled blocks against
+    the oracle, and the whole output equal to one lane per PB."""
+    st = c3_streams[K]
+    n, gens, L, D = st["n"], st["gens"], 6 * K, 512
+    log("C3 K=%d D=512 lanes=%d full stream" % (K, lanes))
+    dsyms = to_dev(torch, st["syms"])
+    with pbvd.Plan(K, gens, D, L, lanes_per_pb=lanes) as plan:
+        got = plan.decode(dsyms, n)
+        nb = plan.num_blocks(n)
+    with pbvd.Plan(K, gens, D, L, lanes_per_pb=1) as plan:
+        one = plan.decode(dsyms, n)
+    torch.cuda.synchronize()
+    assert torch.equal(got, one)
+    bits = gpu_bits(torch, got, n)
+    rng = np.random.default_rng(K * lanes)
+    for b in [0, nb - 1] + sorted(rng.choice(np.arange(1, nb - 1), 6, replace=False).tolist()):
+        ref = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=b, pb_count=1)
+        assert np.array_equal(bits[b * D: b * D + ref["bits"].size], ref["bits"]), "PB %d" % b
+    check_range(torch, pbvd, st, D, L, 16, nb // 3, 3, survivors=True, lanes=lanes)
 
 
 def test_split_invariance_and_misaligned_output(torch, pbvd):
