@@ -217,7 +217,7 @@ def bench_batched(torch, steps: int):
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
     codes, table = autotune.tune_batch_d(torch, base, frames, syms, out)
     D = codes[0]["D"]
-    log("batched: tuned D=%d" % D)
+    log("batched: tuned D=%d lanes=%d" % (D, codes[0]["lanes_per_pb"]))
     with pbvd.Batch(codes) as b:
         b.set_frames(frames, syms.numel(), out.numel())
         info = b.info()
@@ -262,7 +262,8 @@ def bench_batched(torch, steps: int):
         "plain_per_frame_same_d_mbps": round(n_bits / t_plain_d / 1e6, 2),
         "speedup_vs_plain_d512": round(t_plain_512 / wall, 1),
         "batched_equals_plain_same_d": same,
-        "tuning_ms": {str(d): round(t * 1e3, 4) for d, t, _ in table},
+        "lanes_per_pb": codes[0]["lanes_per_pb"],
+        "tuning_ms": {"D%d_lanes%d" % dl: round(t * 1e3, 4) for dl, t, _ in table},
     }
 
 
@@ -407,6 +408,7 @@ def main():
                         "int8 soft at Eb/N0=3 dB, D=512, L=42, int16 path metrics, "
                         "zero-terminated" % args.log2_bits,
             "n_bits": n, "K": K, "R": 2, "D": D, "L": L, "parallel_blocks": plan.num_blocks(n),
+            "lanes_per_pb": plan.call_lanes(n),
         },
         "roofline": {
             "bound": "alu",

@@ -143,6 +143,13 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
 pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
                              int32_t n_streams, int64_t chunk_pbs, uint32_t flags);
 
+/* Lanes per PB (1, 2 or 4) that pbvd_decode_ex of PBs [pb_first, pb_first +
+ * pb_count) of an n_bits-bit stream uses: the plan's lanes_per_pb, or with 0
+ * the library's choice (pairs of lanes where the code allows them when that
+ * still gives 1024 waves, else the largest group the code allows).  0 on
+ * invalid arguments. */
+int32_t pbvd_call_lanes(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count);
+
 /* Number of parallel blocks of a stream: ceil(n_bits / D); 0 if n_bits < 1. */
 int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits);
 

@@ -39,17 +39,54 @@ def time_batch(torch, codes, frames, syms_dev, out_dev, reps: int = 5, warmup: i
         return ts[len(ts) // 2], b.info()
 
 
+def lanes_allowed(code, lanes: int) -> bool:
+    """Lane-group widths the library supports for a code (16-bit metrics,
+    at least 16 packed registers per lane)."""
+    if lanes == 1:
+        return True
+    return (code.get("pm_bits", 16) == 16 and lanes in (2, 4)
+            and (1 << (code["K"] - 2)) // lanes >= 16)
+
+
 def tune_batch_d(torch, codes, frames, syms_dev, out_dev,
-                 d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512), reps: int = 5):
-    """One D for all codes, the fastest batched decode of `frames`.
-    Returns (codes with D filled in, [(D, seconds, info)])."""
+                 d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512),
+                 lane_candidates=(1, 2), reps: int = 5):
+    """One D for all codes and one lane-group width per run (codes that do
+    not support it keep one lane), the fastest batched decode of `frames`.
+    Returns (codes with D and lanes_per_pb filled in, [((D, lanes), seconds,
+    info)])."""
     table = []
-    for d in d_candidates:
-        cs = [dict(c, D=int(d)) for c in codes]
-        t, info = time_batch(torch, cs, frames, syms_dev, out_dev, reps=reps)
-        table.append((int(d), t, info))
-    best = min(table, key=lambda r: r[1])[0]
-    return [dict(c, D=best) for c in codes], table
+    for lanes in lane_candidates:
+        for d in d_candidates:
+            cs = [dict(c, D=int(d), lanes_per_pb=lanes if lanes_allowed(c, lanes) else 1)
+                  for c in codes]
+            t, info = time_batch(torch, cs, frames, syms_dev, out_dev, reps=reps)
+            table.append(((int(d), lanes), t, info))
+    (best_d, best_l) = min(table, key=lambda r: r[1])[0]
+    return [dict(c, D=best_d, lanes_per_pb=best_l if lanes_allowed(c, best_l) else 1)
+            for c in codes], table
+
+
+def tune_plan_lanes(torch, K, gens, D, L, syms_dev, n_bits, out_dev, reps: int = 5, **plan_kw):
+    """The fastest lane-group width for decoding one stream with pbvd_decode.
+    Returns (lanes, {lanes: seconds})."""
+    res = {}
+    for lanes in (1, 2, 4):
+        if not lanes_allowed(dict(K=K, **plan_kw), lanes):
+            continue
+        with pbvd.Plan(K, gens, D, L, lanes_per_pb=lanes, **plan_kw) as p:
+            for _ in range(2):
+                p.decode(syms_dev, n_bits, out=out_dev)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                p.decode(syms_dev, n_bits, out=out_dev)
+            e1.record()
+            e1.synchronize()
+            res[lanes] = e0.elapsed_time(e1) * 1e-3 / reps
+    return min(res, key=res.get), res
 
 
 def serve_load(srv, pool, rate: float, seconds: float, seed: int = 1):

@@ -272,13 +272,17 @@ int64_t waves_per_launch(const pbvd_plan *p, int64_t sp_wave_dwords) {
     return w < 1 ? 1 : w;
 }
 
-// Lanes per PB of one call: the code's choice, or else one lane per PB when
-// that already gives every SIMD a wave, the largest group otherwise.
+// Lanes per PB of one call: the code's choice, or else pairs of lanes where
+// the code allows them (fewer registers per lane, so more waves hide each
+// other's latency) when that gives every SIMD a wave, the largest group
+// otherwise.
 int call_lb(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
     const int req = requested_lb(p->code);
     if (req >= 0) return req;
-    const CallGeometry g0 = call_geometry(p->code, n_bits, pb_first, pb_count, 0);
-    return g0.n_waves >= 1024 ? 0 : max_lb(p->code);
+    const int top = max_lb(p->code);
+    const int pair = top < 1 ? top : 1;
+    const CallGeometry g = call_geometry(p->code, n_bits, pb_first, pb_count, pair);
+    return g.n_waves >= 1024 ? pair : top;
 }
 
 pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
@@ -409,6 +413,11 @@ pbvd_status pbvd_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, uint8_
     if (n_bits < 1) return fail(PBVD_EINVAL, "n_bits must be >= 1 (got %lld)", (long long)n_bits);
     return pbvd_decode_ex(p, d_syms, n_bits, 0, ceil_div(n_bits, p->code.D), d_out_bits, nullptr,
                           hip_stream);
+}
+
+int32_t pbvd_call_lanes(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
+    if (!p || n_bits < 1 || pb_first < 0 || pb_count < 0) return 0;
+    return 1 << call_lb(p, n_bits, pb_first, pb_count);
 }
 
 int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits) {

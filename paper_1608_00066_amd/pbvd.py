@@ -68,6 +68,7 @@ SIGNATURES = {
     "pbvd_decode_ex": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
     "pbvd_decode_host": (_I32, [_P, _P, _I64, _P, _I32, _I64, ctypes.c_uint32]),
     "pbvd_num_blocks": (_I64, [_P, _I64]),
+    "pbvd_call_lanes": (_I32, [_P, _I64, _I64, _I64]),
     "pbvd_block_geometry": (_I32, [_P, _I64, _I64, _I64, _P]),
     "pbvd_debug_survivors": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
     "pbvd_debug_branch_metrics": (_I32, [_P, _P, _I64, _P, _P]),
@@ -195,6 +196,12 @@ class Plan:
 
     def num_blocks(self, n_bits: int) -> int:
         return pbvd_num_blocks(self.handle, n_bits)
+
+    def call_lanes(self, n_bits: int, pb_first: int = 0, pb_count: int | None = None) -> int:
+        """Lanes per PB a decode of these PBs uses (pbvd_call_lanes)."""
+        if pb_count is None:
+            pb_count = self.num_blocks(n_bits) - pb_first
+        return int(lib().pbvd_call_lanes(ctypes.c_void_p(self.handle), n_bits, pb_first, pb_count))
 
     def block_geometry(self, n_bits: int, pb_first: int = 0, pb_count: int | None = None):
         if pb_count is None:

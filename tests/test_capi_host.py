@@ -158,3 +158,26 @@ def test_decode_host_validation(pbvd):
         assert L.pbvd_decode_host(plan, sp, 0, op, 2, 2, 0) == -1
     finally:
         pbvd.pbvd_destroy(h)
+
+
+def test_call_lanes_choice(pbvd):
+    """Lanes per PB: explicit widths are kept, unsupported ones refused, and
+    the library's choice follows the documented rule."""
+    cases = [(7, (0o171, 0o133), 512, 1 << 27, 2), (7, (0o171, 0o133), 512, 1 << 20, 2),
+             (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 4),
+             (5, (0o23, 0o35), 512, 1 << 27, 1), (8, (0o247, 0o371), 64, 64 * 32 * 1024, 2),
+             (8, (0o247, 0o371), 64, 64 * 32 * 1000, 4)]
+    for K, gens, D, n, want in cases:
+        with pbvd.Plan(K, gens, D, 6 * K) as p:
+            assert p.call_lanes(n) == want, (K, n)
+        with pbvd.Plan(K, gens, D, 6 * K, lanes_per_pb=1) as p:
+            assert p.call_lanes(n) == 1
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Plan(7, (0o171, 0o133), 512, 42, lanes_per_pb=4)
+    assert ei.value.status == pbvd.PBVD_ENOTSUP
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Plan(7, (0o171, 0o133), 512, 42, pm_bits=32, lanes_per_pb=2)
+    assert ei.value.status == pbvd.PBVD_ENOTSUP
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Plan(7, (0o171, 0o133), 512, 42, lanes_per_pb=3)
+    assert ei.value.status == pbvd.PBVD_EINVAL
