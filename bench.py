@@ -301,8 +301,8 @@ def bench_serving(seconds: float, rates=(2000, 5000, 10000, 20000, 50000)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--log2-bits", type=int, default=27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
@@ -365,13 +365,13 @@ def main():
             d_s2 = torch.from_numpy(s2["syms"]).cuda()
             o2 = torch.empty((n2 + 7) // 8, dtype=torch.uint8, device="cuda")
             with pbvd.Plan(k2, g2, d2, l2, True, datagen.SOFT_I8, 16) as p2:
-                ms2, kms2 = time_decode(torch, p2, d_s2, n2, o2, max(3, args.steps // 4), 2)
+                ms2, kms2 = time_decode(torch, p2, d_s2, n2, o2, max(3, args.steps // 4), 20)
             extras[tag + "_mbps"] = round(n2 / (ms2 * 1e-3) / 1e6, 1)
             del d_s2, o2, s2
         sweep = {}
         for d2 in (256, 1024, 2048):
             with pbvd.Plan(K, gens, d2, L, True, datagen.SOFT_I8, 16) as p2:
-                ms2, _ = time_decode(torch, p2, syms, n, out, max(3, args.steps // 4), 2)
+                ms2, _ = time_decode(torch, p2, syms, n, out, max(3, args.steps // 4), 20)
             sweep[str(d2)] = round(n / (ms2 * 1e-3) / 1e6, 1)
         extras["k7_r2_2p%d_mbps_by_d" % args.log2_bits] = sweep
         log("host pipeline")

@@ -145,9 +145,9 @@ pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, u
 
 /* Lanes per PB (1, 2 or 4) that pbvd_decode_ex of PBs [pb_first, pb_first +
  * pb_count) of an n_bits-bit stream uses: the plan's lanes_per_pb, or with 0
- * the library's choice (pairs of lanes where the code allows them when that
- * still gives 1024 waves, else the largest group the code allows).  0 on
- * invalid arguments. */
+ * the library's choice: one lane for K <= 7 when that gives 4096 waves of 64
+ * PBs, else pairs of lanes where the code allows them when that gives 1024
+ * waves, else the largest group the code allows.  0 on invalid arguments. */
 int32_t pbvd_call_lanes(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count);
 
 /* Number of parallel blocks of a stream: ceil(n_bits / D); 0 if n_bits < 1. */

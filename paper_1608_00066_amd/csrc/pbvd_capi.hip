@@ -272,17 +272,19 @@ int64_t waves_per_launch(const pbvd_plan *p, int64_t sp_wave_dwords) {
     return w < 1 ? 1 : w;
 }
 
-// Lanes per PB of one call: the code's choice, or else pairs of lanes where
-// the code allows them (fewer registers per lane, so more waves hide each
-// other's latency) when that gives every SIMD a wave, the largest group
-// otherwise.
+// Lanes per PB of one call: the code's choice, or else
+//   one lane per PB for trellises of at most 64 states (32 packed registers)
+//   when that gives 4 waves per SIMD (4096): enough to hide latency;
+//   pairs of lanes where the code allows them when that gives every SIMD a
+//   wave (fewer registers per lane, so more waves hide each other's latency);
+//   the largest group the code allows otherwise (short streams).
 int call_lb(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
     const int req = requested_lb(p->code);
     if (req >= 0) return req;
     const int top = max_lb(p->code);
-    const int pair = top < 1 ? top : 1;
-    const CallGeometry g = call_geometry(p->code, n_bits, pb_first, pb_count, pair);
-    return g.n_waves >= 1024 ? pair : top;
+    if (top == 0) return 0;
+    if (p->code.K <= 7 && call_geometry(p->code, n_bits, pb_first, pb_count, 0).n_waves >= 4096) return 0;
+    return call_geometry(p->code, n_bits, pb_first, pb_count, 1).n_waves >= 1024 ? 1 : top;
 }
 
 pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,

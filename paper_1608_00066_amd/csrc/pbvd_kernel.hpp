@@ -133,6 +133,14 @@ __device__ __forceinline__ uint32_t u_to_idx(uint32_t u) {
 
 // ---------------------------------------------------------------------------
 // Packed path-metric pairs
+// on-lanes of a wave-constant lane pattern take b, the others a: one
+// v_cndmask_b32 with the pattern in a scalar register pair
+__device__ __forceinline__ int select_lanes(int a, int b, uint64_t pattern) {
+    int r;
+    asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(pattern));
+    return r;
+}
+
 // Value of v in another lane of the same quad (DPP quad_perm control CTRL).
 template <int CTRL>
 __device__ __forceinline__ int dpp_int(int v) {
@@ -403,13 +411,6 @@ __host__ __device__ constexpr int lane_code_mask(int PH, int j) {
     if (PH >= kCross && PH < V - 1 && PH - kCross == j) return C::gcol(C::K - 1);
     return C::out0(rotr_v<V>(1 << (kCross + j), PH));
 }
-// masks of all phases packed R bits per phase (phase PH at bit R*PH)
-template <class C, int LB>
-__host__ __device__ constexpr uint32_t lane_code_mask_pack(int j) {
-    uint32_t m = 0;
-    for (int ph = 0; ph < C::V; ++ph) m |= (uint32_t)lane_code_mask<C, LB>(ph, j) << (C::R * ph);
-    return m;
-}
 
 // ---------------------------------------------------------------------------
 // Compile-time layout constants of one code
@@ -506,26 +507,27 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
 #pragma unroll
         for (int r = 0; r < NR; ++r) pm[r] = P::make(r == 0 ? zero : big, big);
     }
-    // code-word relabel masks of this lane, R bits per phase
-    uint32_t lane_masks = 0;
-    if constexpr (LB >= 1) lane_masks ^= (ell & 1) ? lane_code_mask_pack<C, LB>(0) : 0u;
-    if constexpr (LB >= 2) lane_masks ^= (ell & 2) ? lane_code_mask_pack<C, LB>(1) : 0u;
-    // branch metrics of stage phase PH for this lane: metric[c ^ mask]
+    // branch metrics of stage phase PH for this lane: metric[c ^ mask], the
+    // mask being the XOR of the masks of the lane's set group bits; lane
+    // bit j of the group is set in the wave-constant lane pattern kBit[j]
+    constexpr uint64_t kBit[2] = {0xaaaaaaaaaaaaaaaaull, 0xccccccccccccccccull};
     auto stage_metrics = [&](auto phc, int (&q)[R], int (&bm)[NC]) PBVD_INLINE_LAMBDA {
         constexpr int PH = decltype(phc)::value;
-        if constexpr (LB == 0) {
-            code_word_metrics<R>(q, bm);
-        } else {
-            int base = 0;
+        code_word_metrics<R>(q, bm);
+        auto relabel = [&](auto mc, auto jc) PBVD_INLINE_LAMBDA {
+            constexpr int M = decltype(mc)::value;
+            if constexpr (M != 0) {
+                int t[NC];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if ((lane_masks >> (R * PH + R - 1 - r)) & 1u) {
-                    base += q[r];
-                    q[r] = -q[r];
-                }
+                for (int c = 0; c < NC; ++c) t[c] = select_lanes(bm[c], bm[c ^ M], kBit[decltype(jc)::value]);
+#pragma unroll
+                for (int c = 0; c < NC; ++c) bm[c] = t[c];
             }
-            code_word_metrics<R>(q, bm, base);
-        }
+        };
+        if constexpr (LB >= 1)
+            relabel(std::integral_constant<int, lane_code_mask<C, LB>(PH, 0)>{}, std::integral_constant<int, 0>{});
+        if constexpr (LB >= 2)
+            relabel(std::integral_constant<int, lane_code_mask<C, LB>(PH, 1)>{}, std::integral_constant<int, 1>{});
     };
     // renormalization reference: the group's first lane's metric of register 0
     auto renorm = [&]() PBVD_INLINE_LAMBDA {

@@ -163,7 +163,8 @@ def test_decode_host_validation(pbvd):
 def test_call_lanes_choice(pbvd):
     """Lanes per PB: explicit widths are kept, unsupported ones refused, and
     the library's choice follows the documented rule."""
-    cases = [(7, (0o171, 0o133), 512, 1 << 27, 2), (7, (0o171, 0o133), 512, 1 << 20, 2),
+    cases = [(7, (0o171, 0o133), 512, 1 << 27, 1), (7, (0o171, 0o133), 512, 1 << 26, 2),
+             (7, (0o171, 0o133), 512, 1 << 20, 2),
              (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 4),
              (5, (0o23, 0o35), 512, 1 << 27, 1), (8, (0o247, 0o371), 64, 64 * 32 * 1024, 2),
              (8, (0o247, 0o371), 64, 64 * 32 * 1000, 4)]
