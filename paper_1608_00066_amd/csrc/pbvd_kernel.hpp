@@ -827,6 +827,17 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
 #ifndef PBVD_BIG_TRELLIS_WAVES_PER_EU
 #define PBVD_BIG_TRELLIS_WAVES_PER_EU 1
 #endif
+// Register target for 64 metric VGPRs per lane (a 256-state trellis on lane
+// pairs or 128 states on one lane, 16-bit metrics): three waves fit without
+// spills.
+#ifndef PBVD_MID_TRELLIS_WAVES_PER_EU
+#define PBVD_MID_TRELLIS_WAVES_PER_EU 3
+#endif
+// MW = VGPRs of path metrics per lane
+template <int MW>
+__host__ __device__ constexpr int waves_per_eu_target() {
+    return MW >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : (MW >= 64 ? PBVD_MID_TRELLIS_WAVES_PER_EU : 1);
+}
 
 // ---------------------------------------------------------------------------
 // Stream kernel: the PBs of one stream (Sec. III-A, Fig. 2).  Interior PBs
@@ -834,7 +845,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
 // ---------------------------------------------------------------------------
 template <class C, class P, int KIND, int LB>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu((C::NR >> LB) >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu_target<(C::NR >> LB) * (int)(sizeof(typename P::T) / 4)>())))
     decode_kernel(const KernelArgs a) {
     using LY = Layout<C, P, LB>;
     constexpr int R = C::R, N = C::N, PW = LY::PW;
@@ -945,7 +956,7 @@ struct TileArgs {
 
 template <class C, class P, int KIND, int LB>
 __global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu((C::NR >> LB) >= 128 ? PBVD_BIG_TRELLIS_WAVES_PER_EU : 1)))
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu_target<(C::NR >> LB) * (int)(sizeof(typename P::T) / 4)>())))
     decode_tiles_kernel(const TileArgs a) {
     using LY = Layout<C, P, LB>;
     const int lane = threadIdx.x & (kWave - 1);
