@@ -213,8 +213,10 @@ pbvd_status pbvd_batch_create(const pbvd_code *codes, int32_t n_codes, pbvd_batc
  * (PBs of all frames, grouped by code, longest first, 64 per wave), uploads
  * it and sizes the device workspace.  sym_bytes / out_bytes are the sizes of
  * the device buffers later passed to pbvd_batch_decode; every frame must lie
- * inside them and output ranges must not overlap.  Synchronous (blocks the
- * calling thread); PBVD_EINVAL on a bad frame (nothing is changed). */
+ * inside them and output ranges must not overlap.  Synchronous: waits for
+ * all work on the device (earlier decodes of this batch may still read the
+ * work list it replaces), then uploads; PBVD_EINVAL on a bad frame (nothing
+ * is changed). */
 pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64_t n_frames,
                                   int64_t sym_bytes, int64_t out_bytes);
 

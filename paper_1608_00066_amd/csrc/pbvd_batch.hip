@@ -273,6 +273,12 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     DeviceGuard dg(b->device);
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", b->device);
     {
+        // earlier decodes of this batch may still read the work list and
+        // the survivor area that are replaced below
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return fail_hip(e, "waiting for earlier decodes");
+    }
+    {
         // streams and events of the fork, made once, outside any capture
         hipError_t e = hipSuccess;
         if (!b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);

@@ -301,3 +301,40 @@ def test_workspace_chunking(torch, pbvd, monkeypatch):
     with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
         got = gpu_bits(torch, plan.decode(dsyms, n), n)
     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_huge_stream_tail_window(torch, pbvd, lanes):
+    """The last 80 PBs of a 2^34-bit stream (64-bit stage, symbol and output
+    offsets), with only their symbols resident: the decoder is given a base
+    address (2^34 x R bytes before the window) at which stage 0 would lie.
+    The same symbols as a short stream give the same bits and final metrics,
+    and the oracle agrees."""
+    import ctypes
+    K, gens, D, L = 7, (0o171, 0o133), 512, 42
+    n = (1 << 34) + 999
+    nb = -(-n // D)
+    first = nb - 80
+    shift = (first - 1) * D              # big stage shift -> short stage 0
+    n_short = n - shift                  # the short stream's PB j is PB j + first - 1
+    st = datagen.make_stream(K, gens, n_short, 3.0, seed=77)
+    d_syms = to_dev(torch, np.concatenate([st["syms"], np.zeros(256, np.uint8)]))
+    base = d_syms.data_ptr() - shift * len(gens)
+    if base <= 0:
+        pytest.skip("device address too low for the virtual base")
+    log("huge stream window: n=%d PBs [%d, %d) lanes=%d" % (n, first, nb, lanes))
+    with pbvd.Plan(K, gens, D, L, lanes_per_pb=lanes) as plan:
+        nbytes = (plan.out_bits(n, first, 80) + 7) // 8
+        out = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+        fpm = torch.zeros((80, 64), dtype=torch.int32, device="cuda")
+        st_code = pbvd.lib().pbvd_decode_ex(ctypes.c_void_p(plan.handle), ctypes.c_void_p(base), n,
+                                            first, 80, ctypes.c_void_p(out.data_ptr()),
+                                            ctypes.c_void_p(fpm.data_ptr()), None)
+        assert st_code == 0, pbvd.pbvd_last_error()
+        short, spm = plan.decode_ex(d_syms, n_short, 1, 80, want_pm=True)
+        torch.cuda.synchronize()
+    assert torch.equal(out, short[:nbytes])
+    assert torch.equal(fpm, spm[:80])
+    ref = oracle.decode(K, gens, D, L, st["syms"], n_short, pb_first=1, pb_count=80, want_pm=True)
+    assert np.array_equal(gpu_bits(torch, out, ref["bits"].size), ref["bits"])
+    assert np.array_equal(fpm.cpu().numpy(), ref["final_pm"])

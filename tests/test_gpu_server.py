@@ -101,3 +101,19 @@ def test_server_concurrent_submitters(pbvd):
     assert not errors, errors
     for (ci, st), out in zip(reqs, results):
         assert np.array_equal(unpack(out, st["n"]), oracle_bits(CODES[ci], st))
+
+
+def test_server_unterminated_hard_int32_mix(pbvd):
+    """Codes whose last block starts its traceback from the best state, hard
+    input with 32-bit metrics, and explicit lane widths, in one server."""
+    codes = [dict(K=3, gens=(0o7, 0o5), D=64, L=16, terminated=False, input_kind=1, pm_bits=32),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=96, L=54, terminated=False),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=64, L=42, lanes_per_pb=1)]
+    reqs = datagen.make_requests(codes, 90, seed=504, median=300, hi=4000)
+    log("server: unterminated / hard / int32 / lanes mix, 90 requests")
+    with pbvd.Server(codes, device_bytes=64 << 20, max_inflight=2, max_batch_frames=16) as srv:
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        res = [srv.wait(t) for t in tickets]
+    for (ci, st), (out, _) in zip(reqs, res):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st)), \
+            "request of %d bits (code %d) differs from the oracle" % (st["n"], ci)
