@@ -4,11 +4,11 @@
 // Submitters hand in one frame each (host symbols, host output buffer).  A
 // worker thread owns `max_inflight` batch slots.  Each slot has a fixed part
 // of the device budget (inputs, outputs, work list, survivor rows), pinned
-// staging buffers and its own streams.  Whenever a slot is free and requests
+// staging buffers and its own stream.  Whenever a slot is free and requests
 // wait, the worker admits as many as fit the slot (FIFO), uploads their
 // symbols and work list with one copy, launches the batched decode kernels
-// (one per code, on forked streams) and the read-back, and returns to
-// admitting; finished slots are reaped by polling their completion events.
+// (one per code, cheapest first) each with its read-back, and returns to
+// admitting; finished codes and slots are reaped by polling their events.
 // So requests that arrive while other batches run are decoded concurrently
 // with them, and a request's bits do not depend on what it was batched with:
 // every frame is decoded exactly as pbvd_decode would decode it alone.
@@ -99,15 +99,12 @@ struct Footprint {
     int64_t device_bytes(const CodeSet &cs) const { return in_bytes(cs) + align_up(out) + sp_bytes(cs); }
 };
 
-// One batch in flight.  Code 0 of the batch runs on `stream` (which also
-// carries the upload), every other code on its own stream forked after the
-// upload.  Each code reads its own results back and signals its own event,
-// so a code's requests finish without waiting for slower codes of the batch;
-// the slot is free again once every code has finished.
+// One batch in flight on the slot's stream: upload, then per code (cheapest
+// first) its kernels, its read-back and its completion event, so a code's
+// requests finish without waiting for slower codes of the batch; the slot
+// is free again once every code has finished.
 struct Slot {
     hipStream_t stream = nullptr;
-    hipStream_t aux[kMaxCodes] = {};
-    hipEvent_t fork = nullptr;
     hipEvent_t done[kMaxCodes] = {};
     uint8_t *dev = nullptr;       // this slot's part of the device arena
     uint8_t *pin_in = nullptr;    // symbols + work list staging
@@ -200,24 +197,24 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
     const pbvd::LaneDesc *d_lanes = reinterpret_cast<const pbvd::LaneDesc *>(sl.dev + lanes_off);
     const pbvd::TileHead *d_heads = reinterpret_cast<const pbvd::TileHead *>(sl.dev + heads_off);
     uint8_t *d_out = sl.dev + out_dev;
-    if (n_active > 1) {
-        e = hipEventRecord(sl.fork, sl.stream);
-        if (e != hipSuccess) return fail_hip(e, "fork event");
-    }
+    // the codes run one after another on the slot's stream, cheapest first
+    // (2^K R), each followed by its read-back and completion event: a code's
+    // requests finish when its own kernel is done, and a slot's work stays on
+    // one hardware queue, so batches in other slots are not queued behind it
+    std::sort(active, active + n_active, [&cs](int x, int y) {
+        const int64_t wx = (int64_t)cs.codes[x].R << cs.codes[x].K;
+        const int64_t wy = (int64_t)cs.codes[y].R << cs.codes[y].K;
+        return wx != wy ? wx < wy : x < y;
+    });
     for (int k = 0; k < n_active; ++k) {
         const int ci = active[k];
-        hipStream_t s = k == 0 ? sl.stream : sl.aux[ci];
-        if (k > 0) {
-            e = hipStreamWaitEvent(s, sl.fork, 0);
-            if (e != hipSuccess) return fail_hip(e, "fork wait");
-        }
         st = launch_group(cs, ci, wl.groups[ci], d_syms, sym_total, d_out, d_lanes, d_heads,
-                          reinterpret_cast<uint32_t *>(sl.dev + sp_off[ci]), wl.groups[ci].n_tiles, s);
+                          reinterpret_cast<uint32_t *>(sl.dev + sp_off[ci]), wl.groups[ci].n_tiles, sl.stream);
         if (st != PBVD_OK) return st;
         e = hipMemcpyAsync(sl.pin_out + out_lo[ci], d_out + out_lo[ci], (size_t)(out_hi[ci] - out_lo[ci]),
-                           hipMemcpyDeviceToHost, s);
+                           hipMemcpyDeviceToHost, sl.stream);
         if (e != hipSuccess) return fail_hip(e, "result read-back");
-        e = hipEventRecord(sl.done[ci], s);
+        e = hipEventRecord(sl.done[ci], sl.stream);
         if (e != hipSuccess) return fail_hip(e, "completion event");
         sl.pending[ci] = true;
         sl.n_pending += 1;
@@ -352,11 +349,8 @@ void release(pbvd_server *sv) {
     (void)hipDeviceSynchronize();
     for (Slot &sl : sv->slots) {
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
-        for (int i = 0; i < kMaxCodes; ++i) {
-            if (sl.aux[i]) (void)hipStreamDestroy(sl.aux[i]);
+        for (int i = 0; i < kMaxCodes; ++i)
             if (sl.done[i]) (void)hipEventDestroy(sl.done[i]);
-        }
-        if (sl.fork) (void)hipEventDestroy(sl.fork);
         if (sl.pin_in) (void)hipHostFree(sl.pin_in);
         if (sl.pin_out) (void)hipHostFree(sl.pin_out);
     }
@@ -400,11 +394,8 @@ pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pb
             Slot &sl = sv->slots[i];
             sl.dev = sv->arena + (int64_t)i * sv->slot_bytes;
             e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming);
-            for (int c = 0; c < cs.n && e == hipSuccess; ++c) {
-                if (c > 0) e = hipStreamCreateWithFlags(&sl.aux[c], hipStreamNonBlocking);
-                if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done[c], hipEventDisableTiming);
-            }
+            for (int c = 0; c < cs.n && e == hipSuccess; ++c)
+                e = hipEventCreateWithFlags(&sl.done[c], hipEventDisableTiming);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.pin_in, (size_t)sv->pin_in_bytes, hipHostMallocDefault);
             if (e == hipSuccess) e = hipHostMalloc((void **)&sl.pin_out, (size_t)sv->pin_out_bytes, hipHostMallocDefault);
         }
