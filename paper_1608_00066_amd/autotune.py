@@ -121,7 +121,7 @@ def serve_load(srv, pool, rate: float, seconds: float, seed: int = 1):
             "mean_batch": round(float(np.mean([i["batch_frames"] for i in infos])), 2)}
 
 
-def tune_server_d(codes, pool_for, rate: float, seconds: float = 0.5, d_candidates=(32, 64, 128),
+def tune_server_d(codes, pool_for, rate: float, seconds: float = 0.5, d_candidates=(16, 32, 64),
                   **server_kw):
     """One D for all codes, the lowest p99 latency at `rate`.  pool_for(codes)
     returns the request pool for codes with D set.  Returns (codes with D

@@ -38,6 +38,7 @@ namespace {
 
 constexpr int kMaxInflight = 8;
 constexpr int64_t kAlign = 256;
+constexpr int64_t kIdleSpinNs = 2000000;  // worker polls 2 ms before it sleeps
 
 int64_t align_up(int64_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -309,6 +310,12 @@ void worker_main(pbvd_server *sv) {
         for (int i = 0; i < sv->cfg.max_inflight; ++i) any_busy = any_busy || sv->slots[i].busy;
         if (!any_busy) {
             if (sv->stop && sv->queue.empty()) break;
+            // idle: poll for a new request for a short while before sleeping,
+            // since waking a sleeping thread costs tens of microseconds
+            lk.unlock();
+            const int64_t spin_end = now_ns() + kIdleSpinNs;
+            while (sv->queued.load() == 0 && now_ns() < spin_end) std::this_thread::yield();
+            lk.lock();
             sv->cv_work.wait(lk, [sv] { return sv->stop || !sv->queue.empty(); });
             continue;
         }
