@@ -699,14 +699,23 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
 
     // ---- traceback (Sec. III-A, Alg. 1) ----
     // The survivor rows of a PB do not depend on the state being traced, so
-    // blocks of TBR rows are loaded one block ahead of their use; only the
-    // bit selection inside a row follows the state.
-    // every lane of a group traces its PB's whole row; the group's first lane
-    // writes the bits
-    constexpr int TBR = NDW_F >= 4 ? 4 : (NDW_F == 2 ? 8 : (16 / S));  // <= 16 stages, <= 32 dwords per block
-    RowStore<NDW_F, kWave * NDW> tb_rows;
+    // they are loaded in blocks of TBR rows, kDepth - 1 blocks ahead of their
+    // use (a ring of kDepth blocks); only the bit selection inside a row
+    // follows the state.  Each lane loads the part of the row it stored (a
+    // lane group's parts make up the PB's row); every lane of a group traces
+    // the same state, takes the word it needs from the lane that holds it,
+    // and the group's first lane writes the bits.
+    // Rows of 4 or more dwords per PB are split: each lane of a group loads
+    // its own part (W = NDW dwords); smaller rows are loaded whole by every
+    // lane of the group (W = NDW_F).
+    constexpr bool kSplit = LB > 0 && NDW_F >= 4;
+    constexpr int W = kSplit ? NDW : NDW_F;
+    constexpr int TBR = W >= 4 ? 4 : (W == 2 ? 8 : (16 / S));  // <= 16 stages, <= 16 dwords per block
+    constexpr int kDepth = 3;
+    RowStore<W, kWave * NDW> tb_rows;
     tb_rows.rsrc = rows.rsrc;
-    tb_rows.lane_off = LB ? (uint32_t)(threadIdx.x & (kWave - 1)) / (1u << LB) * (NDW_F * 4) : rows.lane_off;
+    tb_rows.lane_off = kSplit || LB == 0 ? rows.lane_off
+                                         : (uint32_t)(threadIdx.x & (kWave - 1)) / (1u << LB) * (NDW_F * 4);
     const bool writer = j.active && ell == 0;
     const int i_lo = j.store0_min;
     const int row_lo = i_lo / S;
@@ -715,7 +724,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     uint32_t word = 0;
     int ph = (len - 1) % V;  // input phase of the stage being traced
 
-    auto load_block = [&](uint32_t (&dst)[TBR][NDW_F], int top) PBVD_INLINE_LAMBDA {
+    auto load_block = [&](uint32_t (&dst)[TBR][W], int top) PBVD_INLINE_LAMBDA {
 #pragma unroll
         for (int t = 0; t < TBR; ++t) {
             const int row = top - t < row_lo ? row_lo : top - t;
@@ -750,7 +759,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     };
 
     // one traceback step at stage i with that stage's survivor row
-    auto step = [&](int i, const uint32_t (&row)[NDW_F], int sub) PBVD_INLINE_LAMBDA {
+    auto step = [&](int i, const uint32_t (&row)[W], int sub) PBVD_INLINE_LAMBDA {
         const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
         bool live = true;
         if constexpr (VARLEN) live = i < j.my_len && i >= j.my_store0;
@@ -765,25 +774,42 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
                 }
             }
             uint32_t dec;
-            if constexpr (NDW_F == 1) {
+            if constexpr (!kSplit && W == 1) {
                 dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
-            } else if constexpr (NDW_F == 2) {
+            } else if constexpr (!kSplit && W == 2) {
                 const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
                 dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
             } else {
-                // select dword idx >> 5 with a binary tree, most significant
-                // index bit first (v[w + half] differs from v[w] in that bit)
-                uint32_t v[NDW_F];
+                // the row's dword idx >> 5: select among this lane's W
+                // dwords with a binary tree, most significant index bit first
+                // (v[w + half] differs from v[w] in that bit) ...
+                uint32_t v[W];
 #pragma unroll
-                for (int w = 0; w < NDW_F; ++w) v[w] = row[w];
-                constexpr int kTopBit = 4 + (NDW_F >= 8 ? 3 : NDW_F >= 4 ? 2 : 1);
+                for (int w = 0; w < W; ++w) v[w] = row[w];
+                constexpr int kLogNdw = W >= 8 ? 3 : W >= 4 ? 2 : W >= 2 ? 1 : 0;
 #pragma unroll
-                for (int half = NDW_F / 2, bit = kTopBit; half >= 1; half /= 2, --bit) {
+                for (int half = W / 2, bit = 4 + kLogNdw; half >= 1; half /= 2, --bit) {
                     const bool up = (idx >> bit) & 1u;
 #pragma unroll
                     for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
                 }
-                dec = (v[0] >> (idx & 31u)) & 1u;
+                uint32_t wsel = v[0];
+                if constexpr (kSplit) {
+                    // ... from the group lane that stored it: lane idx >> (5 + log NDW)
+                    const uint32_t owner = (idx >> (5 + kLogNdw)) & ((1u << LB) - 1);
+                    if constexpr (LB == 1) {
+                        const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 2, 2)>((int)wsel);
+                        const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 3, 3)>((int)wsel);
+                        wsel = owner ? b1 : b0;
+                    } else {
+                        const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 0, 0)>((int)wsel);
+                        const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 1, 1)>((int)wsel);
+                        const uint32_t b2 = (uint32_t)dpp_int<quad_sel(2, 2, 2, 2)>((int)wsel);
+                        const uint32_t b3 = (uint32_t)dpp_int<quad_sel(3, 3, 3, 3)>((int)wsel);
+                        wsel = owner & 2u ? (owner & 1u ? b3 : b2) : (owner & 1u ? b1 : b0);
+                    }
+                }
+                dec = (wsel >> (idx & 31u)) & 1u;
             }
             idx = (idx & ~(1u << qpos)) | (dec << qpos);
         }
@@ -791,7 +817,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     };
 
     // trace rows top..top-TBR+1; false once the first traced stage is passed
-    auto run_block = [&](const uint32_t (&blk)[TBR][NDW_F], int top) PBVD_INLINE_LAMBDA {
+    auto run_block = [&](const uint32_t (&blk)[TBR][W], int top) PBVD_INLINE_LAMBDA {
         return static_for<0, TBR>([&](auto tc) PBVD_INLINE_LAMBDA {
             constexpr int t = decltype(tc)::value;
             const int row = top - t;
@@ -807,16 +833,23 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         });
     };
 
-    uint32_t ra[TBR][NDW_F], rb[TBR][NDW_F];
+    // ring of kDepth blocks: kDepth - 1 loaded ahead, the slot consumed last
+    // is refilled before the next block is traced
+    uint32_t ring[kDepth][TBR][W];
     int top = row_hi;
-    load_block(ra, top);
+    static_for<0, kDepth - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+        load_block(ring[decltype(dc)::value], top - decltype(dc)::value * TBR);
+        return true;
+    });
     for (;;) {
-        load_block(rb, top - TBR);
-        if (!run_block(ra, top)) break;
-        top -= TBR;
-        load_block(ra, top - TBR);
-        if (!run_block(rb, top)) break;
-        top -= TBR;
+        const bool more = static_for<0, kDepth>([&](auto dc) PBVD_INLINE_LAMBDA {
+            constexpr int d = decltype(dc)::value;
+            load_block(ring[(d + kDepth - 1) % kDepth], top - (kDepth - 1) * TBR);
+            if (!run_block(ring[d], top)) return false;
+            top -= TBR;
+            return true;
+        });
+        if (!more) break;
     }
 }
 
