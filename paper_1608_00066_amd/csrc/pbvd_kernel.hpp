@@ -758,9 +758,17 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         }
     };
 
+    // bit position of the traced state's input bit at each phase, 4 bits per
+    // phase (V <= 8), so a step finds it with shifts instead of branches
+    constexpr uint32_t kQpos = [] {
+        uint32_t t = 0;
+        for (int p = 0; p < V; ++p) t |= (uint32_t)ubit_pos<V, LY::kBytePerm>(p) << (4 * p);
+        return t;
+    }();
+
     // one traceback step at stage i with that stage's survivor row
     auto step = [&](int i, const uint32_t (&row)[W], int sub) PBVD_INLINE_LAMBDA {
-        const int qpos = ubit_pos<V, LY::kBytePerm>(ph);
+        const int qpos = (int)((kQpos >> (4 * ph)) & 15u);
         bool live = true;
         if constexpr (VARLEN) live = i < j.my_len && i >= j.my_store0;
         if (live) {
