@@ -87,12 +87,12 @@ typedef struct {
     int32_t input_kind; /* PBVD_SOFT_I8 or PBVD_HARD_U8 */
     int32_t pm_bits;    /* path-metric width, 16 or 32 (32 needs K <= 8);
                            results are identical, only the kernel differs */
-    int32_t lanes_per_pb; /* GPU lanes sharing one PB's trellis: 1, 2 or 4, or
-                           0 to let the library choose per call.  2 and 4 need
-                           pm_bits = 16 and K >= 7 (2) or K >= 8 (4).  More
-                           lanes per PB cut a PB's latency and let short
-                           streams fill more of the GPU; results are
-                           identical, only the kernel differs */
+    int32_t lanes_per_pb; /* GPU lanes sharing one PB's trellis: 1, 2, 4 or
+                           8, or 0 to let the library choose per call.  2, 4
+                           and 8 need pm_bits = 16 and K >= 7 (2), K >= 8 (4)
+                           or K = 9 (8).  More lanes per PB cut a PB's latency
+                           and let short streams fill more of the GPU; results
+                           are identical, only the kernel differs */
 } pbvd_code;
 
 /* Validate `code`, build the trellis tables and pick the kernel.
@@ -143,7 +143,7 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
 pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
                              int32_t n_streams, int64_t chunk_pbs, uint32_t flags);
 
-/* Lanes per PB (1, 2 or 4) that pbvd_decode_ex of PBs [pb_first, pb_first +
+/* Lanes per PB (1, 2, 4 or 8) that pbvd_decode_ex of PBs [pb_first, pb_first +
  * pb_count) of an n_bits-bit stream uses: the plan's lanes_per_pb, or with 0
  * the library's choice: one lane for K <= 7 when that gives 4096 waves of 64
  * PBs, else pairs of lanes where the code allows them when that gives 1024

@@ -44,7 +44,7 @@ def lanes_allowed(code, lanes: int) -> bool:
     at least 16 packed registers per lane)."""
     if lanes == 1:
         return True
-    return (code.get("pm_bits", 16) == 16 and lanes in (2, 4)
+    return (code.get("pm_bits", 16) == 16 and lanes in (2, 4, 8)
             and (1 << (code["K"] - 2)) // lanes >= 16)
 
 
@@ -71,7 +71,7 @@ def tune_plan_lanes(torch, K, gens, D, L, syms_dev, n_bits, out_dev, reps: int =
     """The fastest lane-group width for decoding one stream with pbvd_decode.
     Returns (lanes, {lanes: seconds})."""
     res = {}
-    for lanes in (1, 2, 4):
+    for lanes in (1, 2, 4, 8):
         if not lanes_allowed(dict(K=K, **plan_kw), lanes):
             continue
         with pbvd.Plan(K, gens, D, L, lanes_per_pb=lanes, **plan_kw) as p:

@@ -107,12 +107,12 @@ int64_t slot_dwords(const pbvd_code &c, int lb) {
 }
 
 int requested_lb(const pbvd_code &c) {
-    return c.lanes_per_pb == 4 ? 2 : c.lanes_per_pb == 2 ? 1 : c.lanes_per_pb == 1 ? 0 : -1;
+    return c.lanes_per_pb == 8 ? 3 : c.lanes_per_pb == 4 ? 2 : c.lanes_per_pb == 2 ? 1 : c.lanes_per_pb == 1 ? 0 : -1;
 }
 
 int max_lb(const pbvd_code &c) {
     int lb = 0;
-    while (lb < 2 && pbvd::lanes_allowed(c.K, c.pm_bits, lb + 1)) ++lb;
+    while (lb < 3 && pbvd::lanes_allowed(c.K, c.pm_bits, lb + 1)) ++lb;
     return lb;
 }
 
@@ -144,11 +144,12 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
         return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
     if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
     if (c.pm_bits == 32 && c.K > 8) return fail(PBVD_ENOTSUP, "32-bit path metrics need K <= 8");
-    if (c.lanes_per_pb != 0 && c.lanes_per_pb != 1 && c.lanes_per_pb != 2 && c.lanes_per_pb != 4)
-        return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2 or 4 (got %d)", c.lanes_per_pb);
+    if (c.lanes_per_pb != 0 && c.lanes_per_pb != 1 && c.lanes_per_pb != 2 && c.lanes_per_pb != 4 &&
+        c.lanes_per_pb != 8)
+        return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2, 4 or 8 (got %d)", c.lanes_per_pb);
     if (c.lanes_per_pb > 1 && !pbvd::lanes_allowed(c.K, c.pm_bits, requested_lb(c)))
         return fail(PBVD_ENOTSUP, "%d lanes per PB need 16-bit metrics and K >= %d", c.lanes_per_pb,
-                    c.lanes_per_pb == 2 ? 7 : 8);
+                    c.lanes_per_pb == 2 ? 7 : c.lanes_per_pb == 4 ? 8 : 9);
     {
         // survivor rows of one wave slot are addressed with 32-bit offsets
         const int64_t row_bytes = 64LL * pbvd::survivor_row_dwords(c.K) * 4;

@@ -36,6 +36,7 @@ hipError_t launch_one(const LaunchRequest &req) {
     case 0: return launch_lb<C, P, KIND, 0>(req);
     case 1: return launch_lb<C, P, KIND, 1>(req);
     case 2: return launch_lb<C, P, KIND, 2>(req);
+    case 3: return launch_lb<C, P, KIND, 3>(req);
     }
     return hipErrorInvalidValue;
 }
@@ -57,6 +58,7 @@ hipError_t launch_tiles_one(const TileLaunchRequest &req) {
     case 0: return launch_tiles_lb<C, P, KIND, 0>(req);
     case 1: return launch_tiles_lb<C, P, KIND, 1>(req);
     case 2: return launch_tiles_lb<C, P, KIND, 2>(req);
+    case 3: return launch_tiles_lb<C, P, KIND, 3>(req);
     }
     return hipErrorInvalidValue;
 }

@@ -52,6 +52,11 @@ __device__ __forceinline__ bool static_for(F &&f) {
     }
 }
 
+// Traceback row blocks kept in flight (a ring; all but one are loaded ahead).
+#ifndef PBVD_TRACEBACK_BLOCKS
+#define PBVD_TRACEBACK_BLOCKS 3
+#endif
+
 struct KernelArgs {
     const uint8_t *syms;    // T*R received symbols, stage-major
     uint8_t *out;           // packed decoded bits (direct path)
@@ -179,6 +184,10 @@ struct PM16 {
     static __device__ __forceinline__ T dpp(T a) {
         return __builtin_bit_cast(T, dpp_int<CTRL>(__builtin_bit_cast(int, a)));
     }
+    template <class F>
+    static __device__ __forceinline__ T each(T a, F f) {
+        return __builtin_bit_cast(T, f(__builtin_bit_cast(int, a)));
+    }
 };
 
 struct PM32 {
@@ -197,6 +206,8 @@ struct PM32 {
     static __device__ __forceinline__ int hi(T a) { return a.y; }
     template <int CTRL>
     static __device__ __forceinline__ T dpp(T a) { return T{dpp_int<CTRL>(a.x), dpp_int<CTRL>(a.y)}; }
+    template <class F>
+    static __device__ __forceinline__ T each(T a, F f) { return T{f(a.x), f(a.y)}; }
 };
 
 // acc | (x << SH) as one v_lshl_or_b32.  Written out so that the compiler
@@ -302,6 +313,18 @@ template <int B> __host__ __device__ constexpr int quad_lo() { return B == 0 ? q
 template <int B> __host__ __device__ constexpr int quad_hi() { return B == 0 ? quad_sel(1, 1, 3, 3) : quad_sel(2, 3, 2, 3); }
 template <int B> __host__ __device__ constexpr int quad_flip() { return B == 0 ? quad_sel(1, 0, 3, 2) : quad_sel(2, 3, 0, 1); }
 template <int LB> __host__ __device__ constexpr int quad_first() { return LB == 1 ? quad_sel(0, 0, 2, 2) : quad_sel(0, 0, 0, 0); }
+// Lane bit 2 (groups of 8) crosses quads: DPP row shifts by 4 inside a row of
+// 16 lanes, written only to the banks (groups of 4 lanes) that need them.
+constexpr int kRowShl4 = 0x104;  // lane l reads lane l + 4 of its row
+constexpr int kRowShr4 = 0x114;  // lane l reads lane l - 4 of its row
+// v of the lane with bit 2 cleared / set (lanes that are that lane keep v)
+__device__ __forceinline__ int bit2_lo(int v) { return __builtin_amdgcn_update_dpp(v, v, kRowShr4, 0xf, 0xa, false); }
+__device__ __forceinline__ int bit2_hi(int v) { return __builtin_amdgcn_update_dpp(v, v, kRowShl4, 0xf, 0x5, false); }
+// v of the lane whose bit 2 differs
+__device__ __forceinline__ int bit2_flip(int v) {
+    const int t = __builtin_amdgcn_update_dpp(v, v, kRowShl4, 0xf, 0x5, false);
+    return __builtin_amdgcn_update_dpp(t, v, kRowShr4, 0xf, 0xa, false);
+}
 
 // ---------------------------------------------------------------------------
 // One trellis stage at compile-time phase PH on the NR >> LB registers of a
@@ -373,8 +396,14 @@ __device__ __forceinline__ void acs_stage(typename P::T (&pm)[C::NR >> LB], cons
         static_for<0, NR>([&](auto xc) PBVD_INLINE_LAMBDA {
             constexpr int X = decltype(xc)::value;
             constexpr int alpha = C::out0(rotr_v<V>(X, PH));
-            const T xv = P::template dpp<quad_lo<B>()>(pm[X]);
-            const T yv = P::template dpp<quad_hi<B>()>(pm[X]);
+            T xv, yv;
+            if constexpr (B < 2) {
+                xv = P::template dpp<quad_lo<B>()>(pm[X]);
+                yv = P::template dpp<quad_hi<B>()>(pm[X]);
+            } else {
+                xv = P::each(pm[X], bit2_lo);
+                yv = P::each(pm[X], bit2_hi);
+            }
             const T a = P::add(xv, pair[alpha]);
             const T b = P::add(yv, pair[alpha ^ G0]);
             pm[X] = P::vmin(a, b);
@@ -439,14 +468,14 @@ struct Layout {
     static_assert(kRenormTrips >= 1, "metric range too small for this code");
     // a lane group must fill whole survivor dwords with the byte-permute
     // layout, so that a PB's row is the same bits as with one lane per PB
-    static_assert(LB == 0 || (LB <= 2 && NR >= 16 && std::is_same<P, PM16>::value),
+    static_assert(LB == 0 || (LB <= 3 && NR >= 16 && std::is_same<P, PM16>::value),
                   "lane groups need 16-bit metrics and at least 16 registers per lane");
 };
 
 // Lane groups a code supports (compile-time mirror of lanes_allowed on the host).
 template <class C, class P, int LB>
 __host__ __device__ constexpr bool lanes_supported() {
-    return LB == 0 || (LB <= 2 && (C::NR >> LB) >= 16 && std::is_same<P, PM16>::value);
+    return LB == 0 || (LB <= 3 && (C::NR >> LB) >= 16 && std::is_same<P, PM16>::value);
 }
 
 template <int V>
@@ -510,7 +539,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     // branch metrics of stage phase PH for this lane: metric[c ^ mask], the
     // mask being the XOR of the masks of the lane's set group bits; lane
     // bit j of the group is set in the wave-constant lane pattern kBit[j]
-    constexpr uint64_t kBit[2] = {0xaaaaaaaaaaaaaaaaull, 0xccccccccccccccccull};
+    constexpr uint64_t kBit[3] = {0xaaaaaaaaaaaaaaaaull, 0xccccccccccccccccull, 0xf0f0f0f0f0f0f0f0ull};
     auto stage_metrics = [&](auto phc, int (&q)[R], int (&bm)[NC]) PBVD_INLINE_LAMBDA {
         constexpr int PH = decltype(phc)::value;
         code_word_metrics<R>(q, bm);
@@ -528,11 +557,14 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
             relabel(std::integral_constant<int, lane_code_mask<C, LB>(PH, 0)>{}, std::integral_constant<int, 0>{});
         if constexpr (LB >= 2)
             relabel(std::integral_constant<int, lane_code_mask<C, LB>(PH, 1)>{}, std::integral_constant<int, 1>{});
+        if constexpr (LB >= 3)
+            relabel(std::integral_constant<int, lane_code_mask<C, LB>(PH, 2)>{}, std::integral_constant<int, 2>{});
     };
     // renormalization reference: the group's first lane's metric of register 0
     auto renorm = [&]() PBVD_INLINE_LAMBDA {
         T ref = P::bcast_lo(pm[0]);
         if constexpr (LB > 0) ref = P::template dpp<quad_first<LB>()>(ref);
+        if constexpr (LB > 2) ref = P::each(ref, bit2_lo);
 #pragma unroll
         for (int r = 0; r < NR; ++r) pm[r] = P::sub(pm[r], ref);
     };
@@ -674,6 +706,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         }
         if constexpr (LB >= 1) m = min(m, dpp_int<quad_flip<0>()>(m));
         if constexpr (LB >= 2) m = min(m, dpp_int<quad_flip<1>()>(m));
+        if constexpr (LB >= 3) m = min(m, bit2_flip(m));
         if (j.argmin) {
             int best = N;
 #pragma unroll
@@ -685,6 +718,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
             }
             if constexpr (LB >= 1) best = min(best, dpp_int<quad_flip<0>()>(best));
             if constexpr (LB >= 2) best = min(best, dpp_int<quad_flip<1>()>(best));
+            if constexpr (LB >= 3) best = min(best, bit2_flip(best));
             idx = u_to_idx<V, LY::kBytePerm>((uint32_t)rotr_rt<V>(best, (V - ph_end) % V));
         }
         if (j.pm_out && j.active) {
@@ -711,7 +745,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     constexpr bool kSplit = LB > 0 && NDW_F >= 4;
     constexpr int W = kSplit ? NDW : NDW_F;
     constexpr int TBR = W >= 4 ? 4 : (W == 2 ? 8 : (16 / S));  // <= 16 stages, <= 16 dwords per block
-    constexpr int kDepth = 3;
+    constexpr int kDepth = PBVD_TRACEBACK_BLOCKS;
     RowStore<W, kWave * NDW> tb_rows;
     tb_rows.rsrc = rows.rsrc;
     tb_rows.lane_off = kSplit || LB == 0 ? rows.lane_off
@@ -810,11 +844,17 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
                         const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 3, 3)>((int)wsel);
                         wsel = owner ? b1 : b0;
                     } else {
+                        // lane owner & 3 of this quad, then for groups of 8
+                        // the other quad's when owner bit 2 differs from ours
                         const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 0, 0)>((int)wsel);
                         const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 1, 1)>((int)wsel);
                         const uint32_t b2 = (uint32_t)dpp_int<quad_sel(2, 2, 2, 2)>((int)wsel);
                         const uint32_t b3 = (uint32_t)dpp_int<quad_sel(3, 3, 3, 3)>((int)wsel);
                         wsel = owner & 2u ? (owner & 1u ? b3 : b2) : (owner & 1u ? b1 : b0);
+                        if constexpr (LB == 3) {
+                            const uint32_t other = (uint32_t)bit2_flip((int)wsel);
+                            wsel = ((owner >> 2) & 1u) != (uint32_t)((ell >> 2) & 1) ? other : wsel;
+                        }
                     }
                 }
                 dec = (wsel >> (idx & 31u)) & 1u;

@@ -82,10 +82,10 @@ __host__ __device__ constexpr int trip_stages(int K) {
     return (K - 1) / gcd_int(K - 1, survivor_row_stages(K)) * survivor_row_stages(K);
 }
 __host__ __device__ constexpr int trip_fetch_dwords(int K, int R) { return (trip_stages(K) * R + 3) / 4 + 1; }
-// Lane groups of 2^lb lanes per PB: 16-bit metrics and at least 16 packed
+// Lane groups of 2^lb lanes per PB (lb <= 3): 16-bit metrics and at least 16 packed
 // registers per lane (the host mirror of lanes_supported<>).
 __host__ __device__ constexpr bool lanes_allowed(int K, int pm_bits, int lb) {
-    return lb == 0 || (lb >= 1 && lb <= 2 && pm_bits == 16 && ((1 << (K - 2)) >> lb) >= 16);
+    return lb == 0 || (lb >= 1 && lb <= 3 && pm_bits == 16 && ((1 << (K - 2)) >> lb) >= 16);
 }
 
 }  // namespace pbvd

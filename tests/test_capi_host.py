@@ -165,7 +165,7 @@ def test_call_lanes_choice(pbvd):
     the library's choice follows the documented rule."""
     cases = [(7, (0o171, 0o133), 512, 1 << 27, 1), (7, (0o171, 0o133), 512, 1 << 26, 2),
              (7, (0o171, 0o133), 512, 1 << 20, 2),
-             (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 4),
+             (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 8),
              (5, (0o23, 0o35), 512, 1 << 27, 1), (8, (0o247, 0o371), 64, 64 * 32 * 1024, 2),
              (8, (0o247, 0o371), 64, 64 * 32 * 1000, 4)]
     for K, gens, D, n, want in cases:
@@ -182,3 +182,6 @@ def test_call_lanes_choice(pbvd):
     with pytest.raises(pbvd.PbvdError) as ei:
         pbvd.Plan(7, (0o171, 0o133), 512, 42, lanes_per_pb=3)
     assert ei.value.status == pbvd.PBVD_EINVAL
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Plan(8, (0o247, 0o371), 512, 48, lanes_per_pb=8)
+    assert ei.value.status == pbvd.PBVD_ENOTSUP

@@ -160,7 +160,7 @@ def test_batch_full_size_tuned(torch, pbvd):
     assert torch.equal(alone, out)
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
 def test_batch_lane_groups(torch, pbvd, lanes):
     """Batches with 2^lb lanes per PB (K=7 takes at most 2): same bits as the
     oracle and as one lane per PB."""

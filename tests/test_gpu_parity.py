@@ -192,13 +192,13 @@ def lane_cases():
     return [c for c in fuzz_cases() if c[1] >= 7 and c[8] == 16]
 
 
-@pytest.mark.parametrize("lanes", [1, 2, 4])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8])
 @pytest.mark.parametrize("case", lane_cases(), ids=lambda c: "f%d" % c[0])
 def test_lane_groups_parity(torch, pbvd, case, lanes):
     """Every lane-group width a code supports gives the oracle's bits, final
     metrics and survivor decisions; unsupported widths are refused."""
     i, K, gens, n, D, L, term, kind, pm, ebn0 = case
-    if lanes == 4 and K < 8:
+    if (lanes == 4 and K < 8) or (lanes == 8 and K < 9):
         with pytest.raises(pbvd.PbvdError) as ei:
             pbvd.Plan(K, gens, D, L, term, kind, pm, lanes)
         assert ei.value.status == pbvd.PBVD_ENOTSUP
@@ -211,7 +211,7 @@ def test_lane_groups_parity(torch, pbvd, case, lanes):
                 lanes=lanes)
 
 
-@pytest.mark.parametrize("K,lanes", [(7, 2), (9, 2), (9, 4)])
+@pytest.mark.parametrize("K,lanes", [(7, 2), (9, 2), (9, 4), (9, 8)])
 def test_lane_groups_full_size_sampled(torch, pbvd, c3_streams, K, lanes):
     """The 2^27-bit streams at D=512 with lane groups: sampled blocks against
     the oracle, and the whole output equal to one lane per PB."""
