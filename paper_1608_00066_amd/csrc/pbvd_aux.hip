@@ -44,17 +44,10 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
         const int64_t f1 = d0 + v.D + v.L > v.T ? v.T : d0 + v.D + v.L;
         uint8_t bit = 0;
         if (d0 + row < f1) {
-            const int64_t pw = kWave >> v.lb;  // PBs per wave
-            int64_t wave;
-            int pbl;                            // the PB's place in its wave
-            if (b >= v.b_lo && b < v.b_hi) {
-                wave = (b - v.b_lo) / pw;
-                pbl = (int)((b - v.b_lo) % pw);
-            } else {
-                const int64_t e = b < v.b_lo ? b - v.pb_first : v.n_head + (b - v.b_hi);
-                wave = v.n_int_waves + e;
-                pbl = 0;
-            }
+            const int pw = kWave >> v.lb;  // PBs per wave
+            const WavePlace wp = wave_place(b, v.pb_first, v.b_lo, v.b_hi, v.n_head, v.n_fold, v.n_int_waves, pw);
+            const int64_t wave = wp.wave;
+            const int slot = wp.slot;     // the PB's place in its wave
             const int i = (int)(d0 + row - f0);       // stage index inside the PB
             const int u = rotl_dyn(state, i + 1, V);  // register map after stage i
             const int r = u & (NR - 1), half = u >> (V - 1);
@@ -66,11 +59,11 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
                 // PB's NR/16 dwords in register order (a lane group stores
                 // them lane by lane, which is the same order)
                 const int ndw = NR / 16;
-                w = base[(int64_t)i * pw * ndw + (int64_t)pbl * ndw + (r >> 4)];
+                w = base[(int64_t)i * pw * ndw + (int64_t)slot * ndw + (r >> 4)];
                 pos = v.byte_perm ? 16 * (r & 1) + 8 * half + ((r & 15) >> 1) : (r & 15) + 16 * half;
             } else {
                 const int S = 16 / NR;
-                w = base[(int64_t)(i / S) * kWave + pbl];
+                w = base[(int64_t)(i / S) * kWave + slot];
                 pos = (i % S) * NR + r + 16 * half;
             }
             bit = (uint8_t)((w >> pos) & 1);

@@ -11,7 +11,7 @@ struct SurvivorView {
     const uint32_t *sp;
     int64_t sp_wave_dwords;
     int64_t T, pb_first, pb_count;
-    int64_t b_lo, b_hi, n_head, n_int_waves;
+    int64_t b_lo, b_hi, n_head, n_fold, n_int_waves;
     int32_t K, D, L;
     int32_t byte_perm;  // survivor bit layout: 1 = byte-permute, 0 = shift
     int32_t lb;         // 2^lb lanes per PB (64 >> lb PBs per wave)

@@ -177,15 +177,24 @@ namespace {
 
 // Block decomposition of one call (Sec. III-A with M = L): PBs with the full
 // forward range [bD-L, bD+D+L) and decoded range [bD, bD+D) are "interior"
-// and go 64 to a wave; the others (stream ends) get a wave each.
+// and go 64 >> lb to a wave; the others (stream ends) fill the slots the
+// interior leaves free (n_fold of them, in wave 0) and then get a wave each.
+// PBs that start their traceback from the best state (the end of an
+// unterminated stream) are not folded: a wave takes all final metrics at one
+// stage.  For the same reason nothing is folded when the caller asks for
+// final metrics.  Folding runs wave 0 with per-lane geometry, a little slower
+// than the others, so it is done only where it saves a wave on the busiest
+// SIMD: when ceil(waves / SIMDs) drops (fold_simds = the device's SIMD count;
+// 0 = never fold).
 struct CallGeometry {
     int64_t T, pb_first, pb_end;
-    int64_t b_lo, b_hi, n_head, n_tail;
+    int64_t b_lo, b_hi, n_head, n_tail, n_fold;
     int64_t n_int_waves, n_waves;
     int64_t out_bits;
 };
 
-CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int64_t pb_count, int lb) {
+CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int64_t pb_count, int lb,
+                           int64_t fold_simds = 0) {
     CallGeometry g{};
     const int64_t D = c.D, L = c.L;
     g.T = n + (c.terminated ? c.K - 1 : 0);
@@ -205,17 +214,55 @@ CallGeometry call_geometry(const pbvd_code &c, int64_t n, int64_t pb_first, int6
         g.b_hi = hi;
         g.n_head = lo - pb_first;
         g.n_tail = g.pb_end - hi;
-        g.n_int_waves = ceil_div(hi - lo, pbvd::kWave >> lb);
+        const int64_t pw = pbvd::kWave >> lb;
+        g.n_int_waves = ceil_div(hi - lo, pw);
+        const int64_t spare = g.n_int_waves * pw - (hi - lo);
+        const int64_t foldable = c.terminated ? g.n_head + g.n_tail : g.n_head;
+        const int64_t n_fold = spare < foldable ? spare : foldable;
+        const int64_t w = g.n_int_waves + g.n_head + g.n_tail;
+        if (fold_simds > 0 && ceil_div(w - n_fold, fold_simds) < ceil_div(w, fold_simds)) g.n_fold = n_fold;
     } else {
         g.b_lo = g.b_hi = g.pb_end;
         g.n_head = pb_count;
         g.n_tail = 0;
         g.n_int_waves = 0;
     }
-    g.n_waves = g.n_int_waves + g.n_head + g.n_tail;
+    g.n_waves = g.n_int_waves + g.n_head + g.n_tail - g.n_fold;
     const int64_t end_bit = g.pb_end * D < n ? g.pb_end * D : n;
     g.out_bits = pb_count > 0 ? end_bit - pb_first * D : 0;
     return g;
+}
+
+// Wide-fetch bounds of wave 0 when it holds folded edge PBs: every lane
+// fetches the symbols of a trip with one window of trip_fetch_dwords dwords,
+// never past its own last trip.  *i_safe is the last trip start at which
+// every lane's window is inside the T*R input bytes; *wide is 1 when all of
+// them are (mirrors the kernel's per-lane geometry of that wave).
+void fold_fetch_bounds(const pbvd_code &c, const CallGeometry &g, int32_t *i_safe, int32_t *wide) {
+    const int64_t D = c.D, L = c.L, R = c.R;
+    const int64_t len = D + 2 * L;
+    *i_safe = (int32_t)len;
+    *wide = 1;
+    if (g.n_fold == 0) return;
+    const int64_t U = pbvd::trip_stages(c.K);
+    const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
+    const int64_t in_bytes = g.T * R;
+    const int64_t n_pb = g.n_fold + (g.b_hi - g.b_lo);
+    int64_t lim = len;
+    for (int64_t s = 0; s < n_pb && s < pbvd::kWave; ++s) {
+        const int64_t b = s < g.n_fold ? (s < g.n_head ? g.pb_first + s : g.b_hi + (s - g.n_head))
+                                       : g.b_lo + (s - g.n_fold);
+        const int64_t d0 = b * D;
+        const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
+        const int64_t f1 = d0 + D + L > g.T ? g.T : d0 + D + L;
+        const int64_t last_trip = ((f1 - f0 - 1) / U) * U;
+        if (f0 * R + last_trip * R + 4 * ND <= in_bytes) continue;
+        *wide = 0;
+        const int64_t room = in_bytes - f0 * R - 4 * ND;
+        const int64_t i = room < 0 ? -1 : room / R;
+        if (i < lim) lim = i;
+    }
+    *i_safe = (int32_t)lim;
 }
 
 }  // namespace
@@ -262,6 +309,7 @@ struct pbvd_plan {
     int ndw;                  // survivor dwords per stored row
     int row_stages;           // stages per stored row
     int64_t budget_bytes;     // survivor workspace limit
+    int64_t n_simd;           // SIMDs of the device (4 per compute unit)
     Workspace ws;             // pbvd_decode / pbvd_decode_ex
     PipeStream pipe[kMaxPipeStreams];
 };
@@ -309,7 +357,7 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
     const pbvd_code &c = p->code;
     const int lb = call_lb(p, n_bits, pb_first, pb_count);
     const int64_t sp_wave_dwords = slot_dwords(c, lb);
-    const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count, lb);
+    const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count, lb, d_final_pm ? 0 : p->n_simd);
     if (geo_out) *geo_out = g;
     if (lb_out) *lb_out = lb;
     if (pb_count == 0) return PBVD_OK;
@@ -347,7 +395,9 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
     a.b_lo = g.b_lo;
     a.b_hi = g.b_hi;
     a.n_head = g.n_head;
+    a.n_fold = g.n_fold;
     a.n_int_waves = g.n_int_waves;
+    fold_fetch_bounds(c, g, &a.fold_i_safe, &a.fold_wide);
     a.out_bytes = out_bytes;
     a.sp_wave_dwords = sp_wave_dwords;
     a.D = c.D;
@@ -394,6 +444,14 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
     p->ndw = pbvd::survivor_row_dwords(c.K);
     p->row_stages = pbvd::survivor_row_stages(c.K);
     p->budget_bytes = workspace_budget_bytes();
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    p->n_simd = 4 * (int64_t)cus;
+    // PBVD_FOLD_SIMDS overrides the SIMD count of the edge-folding rule
+    // (1: fold whenever it saves a wave, 0: never fold)
+    if (const char *env = getenv("PBVD_FOLD_SIMDS")) p->n_simd = atoll(env) < 0 ? 0 : atoll(env);
     *out = p;
     return PBVD_OK;
 }
@@ -474,6 +532,7 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     v.b_lo = g.b_lo;
     v.b_hi = g.b_hi;
     v.n_head = g.n_head;
+    v.n_fold = g.n_fold;
     v.n_int_waves = g.n_int_waves;
     v.K = p->code.K;
     v.D = p->code.D;

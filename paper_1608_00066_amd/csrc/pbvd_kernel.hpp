@@ -68,7 +68,8 @@ struct KernelArgs {
     int64_t pb_first;       // first PB of this call
     int64_t b_lo, b_hi;     // interior PBs (full geometry) of this call
     int64_t n_head;         // edge PBs [pb_first, pb_first + n_head) precede b_lo
-    int64_t n_int_waves;    // waves covering [b_lo, b_hi), 64 >> LB PBs each
+    int64_t n_fold;         // edge PBs placed in the first wave's leading slots
+    int64_t n_int_waves;    // waves covering n_fold + (b_hi - b_lo) slots, 64 >> LB PBs each
     int64_t wave_begin;     // first wave (interior waves first, then edge waves)
     int64_t n_waves;        // waves in this launch
     int64_t out_bytes;      // bytes of `out`
@@ -76,7 +77,29 @@ struct KernelArgs {
     int32_t D, L;
     int32_t terminated;
     int32_t direct_out;     // 1: plain stores into out, 0: atomic OR into out_words
+    int32_t fold_i_safe;    // first wave with folded PBs: last trip start whose wide fetch is in bounds
+    int32_t fold_wide;      // first wave with folded PBs: every wide fetch is in bounds
 };
+
+// Place of PB b in the stream kernel's waves.  Edge PBs (clipped geometry at
+// the stream ends) are numbered stream-start PBs first, then stream-end PBs;
+// the first n_fold of them take the leading slots of wave 0, the interior PBs
+// fill the slots after them 64 >> LB to a wave, and every other edge PB gets
+// a wave of its own after the interior waves (slot 0).
+struct WavePlace {
+    int64_t wave;
+    int slot;
+};
+__host__ __device__ inline WavePlace wave_place(int64_t b, int64_t pb_first, int64_t b_lo, int64_t b_hi,
+                                                int64_t n_head, int64_t n_fold, int64_t n_int_waves, int pw) {
+    if (b >= b_lo && b < b_hi) {
+        const int64_t s = n_fold + (b - b_lo);
+        return {s / pw, (int)(s % pw)};
+    }
+    const int64_t e = b < b_lo ? b - pb_first : n_head + (b - b_hi);
+    if (e < n_fold) return {0, (int)e};
+    return {n_int_waves + (e - n_fold), 0};
+}
 
 // ---------------------------------------------------------------------------
 // Code description (compile-time generators)
@@ -922,7 +945,11 @@ __host__ __device__ constexpr int waves_per_eu_target() {
 
 // ---------------------------------------------------------------------------
 // Stream kernel: the PBs of one stream (Sec. III-A, Fig. 2).  Interior PBs
-// (full geometry) go 64 to a wave; PBs at the stream ends get a wave each.
+// (full geometry) go 64 to a wave.  PBs at the stream ends take the free
+// slots the interior leaves (moved to the front of wave 0), so that they add
+// no wave of their own while there is room; the others get a wave each.
+// Waves of one SIMD run nearly one after another (the oldest wave issues
+// first), so a single extra wave lengthens the whole launch by its share.
 // ---------------------------------------------------------------------------
 template <class C, class P, int KIND, int LB>
 __global__ void __launch_bounds__(256)
@@ -941,13 +968,64 @@ __global__ void __launch_bounds__(256)
     const int64_t wave = a.wave_begin + wave_local;
     const int64_t D = a.D, L = a.L;
 
+    RowStore<LY::NDW> rows;
+    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
+                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
+    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
+    WaveJob j;
+    j.out_mode = a.direct_out ? kOutDirect : kOutAtomic;
+    j.out = a.out;
+    j.out_bytes = a.out_bytes;
+    j.out_words = a.out_words;
+    j.in_end = a.syms + a.T * R;
+
+    if (wave == 0 && a.n_fold > 0) {
+        // ---- wave 0 with folded edge PBs: every lane has its own geometry
+        //      (Sec. III-A, clipped to the stream), decoded like a batch tile.
+        //      A lane shorter than the wave runs on past its own end, so its
+        //      metrics at the wave's end are not its final metrics: the host
+        //      folds no PB that starts its traceback from the best state and
+        //      folds nothing when final metrics are asked for. ----
+        int64_t b;
+        bool active = true;
+        if (pl < a.n_fold) {
+            b = pl < a.n_head ? a.pb_first + pl : a.b_hi + (pl - a.n_head);
+        } else {
+            b = a.b_lo + (pl - a.n_fold);
+            if (b >= a.b_hi) {
+                b = a.b_hi - 1;
+                active = false;
+            }
+        }
+        const int64_t d0 = b * D;
+        const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
+        const int64_t f1 = d0 + D + L > a.T ? a.T : d0 + D + L;
+        const int64_t d1 = d0 + D > a.n ? a.n : d0 + D;
+        j.len = (int)(D + 2 * L);
+        j.store0_min = a.n_head > 0 ? (int)(a.pb_first * D) : (int)L;
+        j.i_safe = a.fold_i_safe;
+        j.fetch_safe = a.fold_wide != 0;
+        j.need_final = false;
+        j.in = a.syms + f0 * R;
+        j.my_len = (int)(f1 - f0);
+        j.my_store0 = (int)(d0 - f0);
+        j.my_dec_end = (int)(d1 - f0);
+        j.known = f0 == 0;
+        j.argmin = false;
+        j.active = active;
+        j.out_bit0 = (b - a.pb_first) * D;
+        j.pm_out = nullptr;
+        decode_body<C, P, KIND, true, LB>(j, rows);
+        return;
+    }
+
     // ---- block geometry (Sec. III-A with M = L, clipped to the stream) ----
     int64_t b, f0w, f1w, d0w, d1w;   // wave-uniform PB geometry (interior: lane 0's)
     bool active;
     int64_t lane_stage_off;           // this lane's stage offset from f0w
     int64_t far_lane;                 // the wave's last real lane
     if (wave < a.n_int_waves) {
-        const int64_t bw = a.b_lo + wave * PW;
+        const int64_t bw = a.b_lo + wave * PW - a.n_fold;
         b = bw + pl;
         active = b < a.b_hi;
         lane_stage_off = (active ? (int64_t)pl : (a.b_hi - 1 - bw)) * D;
@@ -958,7 +1036,7 @@ __global__ void __launch_bounds__(256)
         f1w = d0w + D + L;
         d1w = d0w + D;
     } else {
-        const int64_t e = wave - a.n_int_waves;
+        const int64_t e = wave - a.n_int_waves + a.n_fold;
         b = e < a.n_head ? a.pb_first + e : a.b_hi + (e - a.n_head);
         active = pl == 0;
         lane_stage_off = 0;
@@ -968,7 +1046,6 @@ __global__ void __launch_bounds__(256)
         f1w = d0w + D + L > a.T ? a.T : d0w + D + L;
         d1w = d0w + D > a.n ? a.n : d0w + D;
     }
-    WaveJob j;
     // stage counts fit in 32 bits (at most D + 2L), which keeps the loop
     // control on the scalar unit
     j.len = (int)(f1w - f0w);
@@ -977,7 +1054,6 @@ __global__ void __launch_bounds__(256)
     j.my_store0 = j.store0_min;
     j.my_dec_end = (int)(d1w - f0w);
     j.in = a.syms + (f0w + lane_stage_off) * R;
-    j.in_end = a.syms + a.T * R;
     // wave-uniform: every wide fetch of every lane stays inside the input;
     // only the last wave(s) of a stream take the byte-load path
     j.fetch_safe = a.syms + (f0w + far_lane * D + (j.len - 1)) * R + 4 * ND <= j.in_end;
@@ -987,17 +1063,8 @@ __global__ void __launch_bounds__(256)
     j.argmin = f1w == a.T && !a.terminated;
     j.need_final = j.argmin || a.final_pm != nullptr;
     j.active = active;
-    j.out_mode = a.direct_out ? kOutDirect : kOutAtomic;
-    j.out = a.out;
-    j.out_bytes = a.out_bytes;
-    j.out_words = a.out_words;
     j.out_bit0 = (b - a.pb_first) * D;
     j.pm_out = a.final_pm ? a.final_pm + (b - a.pb_first) * N : nullptr;
-
-    RowStore<LY::NDW> rows;
-    rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
-                                                  (int)(a.sp_wave_dwords * 4), kBufferFlags);
-    rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
     decode_body<C, P, KIND, false, LB>(j, rows);
 }
 

@@ -69,6 +69,19 @@ def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=Tr
         mism = np.flatnonzero(got_bits != ref["bits"])
         assert mism.size == 0, "bit mismatches at %s" % mism[:10]
         assert np.array_equal(got_pm, ref["final_pm"]), "final metric mismatch"
+        # without final metrics, PBs at the stream ends share the first wave
+        # with interior PBs wherever that saves a wave (PBVD_FOLD_SIMDS=1)
+        prev = os.environ.get("PBVD_FOLD_SIMDS")
+        os.environ["PBVD_FOLD_SIMDS"] = "1"
+        try:
+            with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes) as fplan:
+                out1, _ = fplan.decode_ex(dsyms, n, pb_first, pb_count)
+                assert np.array_equal(gpu_bits(torch, out1, nbits), ref["bits"]), "bits with folding"
+        finally:
+            if prev is None:
+                del os.environ["PBVD_FOLD_SIMDS"]
+            else:
+                os.environ["PBVD_FOLD_SIMDS"] = prev
         if survivors:
             out2, dec = plan.debug_survivors(dsyms, n, pb_first, pb_count)
             assert np.array_equal(gpu_bits(torch, out2, nbits), ref["bits"])
@@ -232,6 +245,62 @@ def test_lane_groups_full_size_sampled(torch, pbvd, c3_streams, K, lanes):
         ref = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=b, pb_count=1)
         assert np.array_equal(bits[b * D: b * D + ref["bits"].size], ref["bits"]), "PB %d" % b
     check_range(torch, pbvd, st, D, L, 16, nb // 3, 3, survivors=True, lanes=lanes)
+
+
+def _edge_counts(n, K, D, L, term, pb_first, pb_count):
+    """(interior, stream-start, stream-end) PB counts of a call: interior PBs
+    have the full forward range [bD-L, bD+D+L) inside the stream (ending
+    before T on an unterminated stream) and a whole decoded range."""
+    T = n + (K - 1 if term else 0)
+    pb_end = pb_first + pb_count
+    lo = max(-(-L // D), pb_first)
+    lim = min(T - D - L - (0 if term else 1), n - D)
+    hi = min(0 if lim < 0 else lim // D + 1, pb_end)
+    if lo >= hi:
+        return 0, pb_count, 0
+    return hi - lo, lo - pb_first, pb_end - hi
+
+
+def _fold_case(K, D, L, term, spare, pw, pb_first=0, tail_pbs=None):
+    """The smallest stream (and PB count) whose interior leaves `spare` free
+    slots in its last wave of pw PBs."""
+    for n in range(D, 200 * D):
+        nb = -(-n // D)
+        count = nb - pb_first if tail_pbs is None else min(nb - pb_first, tail_pbs)
+        if count <= 0:
+            continue
+        n_int, n_head, n_tail = _edge_counts(n, K, D, L, term, pb_first, count)
+        if n_int > pw and (-n_int) % pw == spare and n_head + n_tail > 0:
+            return n, count, n_head, n_tail
+    raise AssertionError("no stream found")
+
+
+@pytest.mark.parametrize("K,D,L,term,spare,lanes,pb_first", [
+    (7, 64, 42, True, 0, 1, 0),     # no free slot: every edge PB gets its own wave
+    (7, 64, 42, True, 1, 1, 0),     # the start PB folds, the end PB does not
+    (7, 64, 42, True, 5, 1, 0),     # both fold
+    (7, 64, 42, False, 5, 1, 0),    # unterminated: only the start PB folds
+    (7, 64, 200, True, 3, 1, 0),    # four start PBs, three fold
+    (7, 64, 200, True, 9, 1, 2),    # a range starting inside the start PBs
+    (7, 24, 42, True, 7, 2, 0),     # pairs of lanes (32 PBs per wave)
+    (9, 32, 54, True, 6, 8, 0),     # groups of 8 lanes (8 PBs per wave)
+    (5, 40, 30, True, 4, 1, 0),     # several stages per survivor row
+])
+def test_edge_blocks_in_free_slots(torch, pbvd, monkeypatch, K, D, L, term, spare, lanes, pb_first):
+    """PBs at the stream ends share the first wave with interior PBs when the
+    interior leaves free slots: bits, final metrics and survivor decisions
+    equal the oracle's for every split of edge PBs between that wave and
+    waves of their own.  (On a whole device the library folds only where it
+    saves a wave on the busiest SIMD; PBVD_FOLD_SIMDS=1 folds whenever a wave
+    is saved.)"""
+    monkeypatch.setenv("PBVD_FOLD_SIMDS", "1")
+    codes = {7: (0o171, 0o133), 9: (0o557, 0o663, 0o711), 5: (0o23, 0o35)}
+    pw = 64 // lanes
+    n, count, n_head, n_tail = _fold_case(K, D, L, term, spare, pw, pb_first)
+    log("edge folding: K=%d D=%d L=%d term=%d n=%d PBs [%d, +%d) start %d end %d spare %d lanes %d"
+        % (K, D, L, term, n, pb_first, count, n_head, n_tail, spare, lanes))
+    st = datagen.make_stream(K, codes[K], n, 2.0, seed=900 + spare + D, terminated=term)
+    check_range(torch, pbvd, st, D, L, 16, pb_first, count, survivors=True, lanes=lanes)
 
 
 def test_split_invariance_and_misaligned_output(torch, pbvd):
