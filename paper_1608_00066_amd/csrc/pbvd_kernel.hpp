@@ -256,6 +256,11 @@ __device__ __forceinline__ uint32_t and_or(uint32_t x, uint32_t mask, uint32_t a
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family)
+// Cache policy of survivor rows: non-temporal.  A row is written once and
+// read once by the traceback, long after it has left the L2, so it should not
+// evict the input symbols that the next loop trips of the same lanes read
+// again (measured: 2.47 -> 1.93 GB fetched per 2^27-bit K=7 launch).
+constexpr int kRowPolicy = 2;  // nt
 
 // A lane moves NDW dwords of a row; consecutive rows are ROW_DW dwords apart
 // (64 lanes x their own dwords when every lane stores its part).
@@ -267,28 +272,28 @@ struct RowStore {
     __device__ __forceinline__ void store(int row, const uint32_t (&v)[NDW]) const {
         const int so = row * kRowBytes;
         if constexpr (NDW == 1) {
-            __builtin_amdgcn_raw_buffer_store_b32(v[0], rsrc, lane_off, so, 0);
+            __builtin_amdgcn_raw_buffer_store_b32(v[0], rsrc, lane_off, so, kRowPolicy);
         } else if constexpr (NDW == 2) {
-            __builtin_amdgcn_raw_buffer_store_b64(u32x2{v[0], v[1]}, rsrc, lane_off, so, 0);
+            __builtin_amdgcn_raw_buffer_store_b64(u32x2{v[0], v[1]}, rsrc, lane_off, so, kRowPolicy);
         } else {
 #pragma unroll
             for (int w = 0; w < NDW; w += 4)
                 __builtin_amdgcn_raw_buffer_store_b128(u32x4{v[w], v[w + 1], v[w + 2], v[w + 3]}, rsrc,
-                                                       lane_off + 4 * w, so, 0);
+                                                       lane_off + 4 * w, so, kRowPolicy);
         }
     }
     __device__ __forceinline__ void load(int row, uint32_t (&v)[NDW]) const {
         const int so = row * kRowBytes;
         if constexpr (NDW == 1) {
-            v[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane_off, so, 0);
+            v[0] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, lane_off, so, kRowPolicy);
         } else if constexpr (NDW == 2) {
-            const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane_off, so, 0);
+            const u32x2 t = __builtin_amdgcn_raw_buffer_load_b64(rsrc, lane_off, so, kRowPolicy);
             v[0] = t.x;
             v[1] = t.y;
         } else {
 #pragma unroll
             for (int w = 0; w < NDW; w += 4) {
-                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rsrc, lane_off + 4 * w, so, 0);
+                const u32x4 t = __builtin_amdgcn_raw_buffer_load_b128(rsrc, lane_off + 4 * w, so, kRowPolicy);
                 v[w] = t.x;
                 v[w + 1] = t.y;
                 v[w + 2] = t.z;
@@ -823,6 +828,131 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         return t;
     }();
 
+    // follow the survivor of the traced state through one stage: its
+    // decision bit in the stage's row (slot idx, + sub * NR for the sub-th
+    // stage of a row) becomes bit qpos of the rotated index
+    auto follow = [&](const uint32_t (&row)[W], int sub, uint32_t qpos) PBVD_INLINE_LAMBDA {
+        uint32_t dec;
+        if constexpr (!kSplit && W == 1) {
+            dec = row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u);
+        } else if constexpr (!kSplit && W == 2) {
+            const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
+            dec = (uint32_t)(r64 >> (idx & 63u));
+        } else {
+            // the row's dword idx >> 5: select among this lane's W
+            // dwords with a binary tree, most significant index bit first
+            // (v[w + half] differs from v[w] in that bit) ...
+            uint32_t v[W];
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] = row[w];
+            constexpr int kLogNdw = W >= 8 ? 3 : W >= 4 ? 2 : W >= 2 ? 1 : 0;
+#pragma unroll
+            for (int half = W / 2, bit = 4 + kLogNdw; half >= 1; half /= 2, --bit) {
+                const bool up = (idx >> bit) & 1u;
+#pragma unroll
+                for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
+            }
+            uint32_t wsel = v[0];
+            if constexpr (kSplit) {
+                // ... from the group lane that stored it: lane idx >> (5 + log NDW)
+                const uint32_t owner = (idx >> (5 + kLogNdw)) & ((1u << LB) - 1);
+                if constexpr (LB == 1) {
+                    const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 2, 2)>((int)wsel);
+                    const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 3, 3)>((int)wsel);
+                    wsel = owner ? b1 : b0;
+                } else {
+                    // lane owner & 3 of this quad, then for groups of 8
+                    // the other quad's when owner bit 2 differs from ours
+                    const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 0, 0)>((int)wsel);
+                    const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 1, 1)>((int)wsel);
+                    const uint32_t b2 = (uint32_t)dpp_int<quad_sel(2, 2, 2, 2)>((int)wsel);
+                    const uint32_t b3 = (uint32_t)dpp_int<quad_sel(3, 3, 3, 3)>((int)wsel);
+                    wsel = owner & 2u ? (owner & 1u ? b3 : b2) : (owner & 1u ? b1 : b0);
+                    if constexpr (LB == 3) {
+                        const uint32_t other = (uint32_t)bit2_flip((int)wsel);
+                        wsel = ((owner >> 2) & 1u) != (uint32_t)((ell >> 2) & 1) ? other : wsel;
+                    }
+                }
+            }
+            dec = wsel >> (idx & 31u);
+        }
+        // only bit 0 of dec is the decision: the insert mask drops the rest
+        const uint32_t m = 1u << qpos;
+        idx = (idx & ~m) | ((dec << qpos) & m);
+    };
+
+    if constexpr (!VARLEN && S == 1) {
+        // ---- one stage per row and one geometry for the whole wave: blocks
+        //      of V rows whose top row is at phase V-1, so every step's bit
+        //      position is a compile-time constant; only the first and the
+        //      last block (and the one holding the decoded range's end) check
+        //      stage bounds. ----
+        constexpr int TB = V;
+        const int i_top = len - 1;
+        const int dec_end = j.my_dec_end;  // decoded stages are [i_lo, dec_end)
+        // take the input bit of stage i (decoded range) into the output word;
+        // a word is complete at a multiple of 32 from the range's start
+        auto take_bit = [&](int i, uint32_t qpos, bool emit) PBVD_INLINE_LAMBDA {
+            word = (word << 1) | ((idx >> qpos) & 1u);
+            if (__builtin_expect(emit, 0)) {  // one step in 32: keep it off the straight path
+                const int rel = i - i_lo;
+                if (writer) put_word(rel, n_dec - rel < 32 ? n_dec - rel : 32);
+                word = 0;
+            }
+        };
+        // KIND 0: every stage is traced and decoded; 1: none is decoded;
+        // 2: bounds and the decoded range's end are checked stage by stage
+        auto run = [&](auto kc, const uint32_t (&blk)[TB][W], int top) PBVD_INLINE_LAMBDA {
+            constexpr int kind = decltype(kc)::value;
+            const int e = (top - i_lo) & 31;  // step whose bit completes a word
+            static_for<0, TB>([&](auto tc) PBVD_INLINE_LAMBDA {
+                constexpr int t = decltype(tc)::value;
+                constexpr uint32_t qpos = ubit_pos<V, LY::kBytePerm>(V - 1 - t);
+                const int i = top - t;
+                if constexpr (kind == 2) {
+                    if (i > i_top || i < i_lo) return true;
+                    if (i < dec_end) take_bit(i, qpos, e == t);
+                } else if constexpr (kind == 0) {
+                    take_bit(i, qpos, e == t);
+                }
+                follow(blk[t], 0, qpos);
+                return true;
+            });
+        };
+        auto load_rows = [&](uint32_t (&dst)[TB][W], int top) PBVD_INLINE_LAMBDA {
+#pragma unroll
+            for (int t = 0; t < TB; ++t) {
+                int row = top - t;
+                row = row > row_hi ? row_hi : (row < row_lo ? row_lo : row);
+                tb_rows.load(row, dst[t]);
+            }
+        };
+        uint32_t ring[kDepth][TB][W];
+        int top = i_top + (V - 1) - i_top % V;  // the first block's top row (phase V-1)
+        static_for<0, kDepth - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+            load_rows(ring[decltype(dc)::value], top - decltype(dc)::value * TB);
+            return true;
+        });
+        for (;;) {
+            const bool more = static_for<0, kDepth>([&](auto dc) PBVD_INLINE_LAMBDA {
+                constexpr int d = decltype(dc)::value;
+                load_rows(ring[(d + kDepth - 1) % kDepth], top - (kDepth - 1) * TB);
+                const int bot = top - TB + 1;
+                if (top > i_top || bot < i_lo || (top >= dec_end && bot < dec_end))
+                    run(std::integral_constant<int, 2>{}, ring[d], top);
+                else if (top < dec_end)
+                    run(std::integral_constant<int, 0>{}, ring[d], top);
+                else
+                    run(std::integral_constant<int, 1>{}, ring[d], top);
+                if (bot <= i_lo) return false;
+                top -= TB;
+                return true;
+            });
+            if (!more) break;
+        }
+        return;
+    }
+
     // one traceback step at stage i with that stage's survivor row
     auto step = [&](int i, const uint32_t (&row)[W], int sub) PBVD_INLINE_LAMBDA {
         const int qpos = (int)((kQpos >> (4 * ph)) & 15u);
@@ -838,51 +968,7 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
                     word = 0;
                 }
             }
-            uint32_t dec;
-            if constexpr (!kSplit && W == 1) {
-                dec = (row[0] >> ((idx + (uint32_t)(sub * NR)) & 31u)) & 1u;
-            } else if constexpr (!kSplit && W == 2) {
-                const uint64_t r64 = ((uint64_t)row[1] << 32) | row[0];
-                dec = (uint32_t)(r64 >> (idx & 63u)) & 1u;
-            } else {
-                // the row's dword idx >> 5: select among this lane's W
-                // dwords with a binary tree, most significant index bit first
-                // (v[w + half] differs from v[w] in that bit) ...
-                uint32_t v[W];
-#pragma unroll
-                for (int w = 0; w < W; ++w) v[w] = row[w];
-                constexpr int kLogNdw = W >= 8 ? 3 : W >= 4 ? 2 : W >= 2 ? 1 : 0;
-#pragma unroll
-                for (int half = W / 2, bit = 4 + kLogNdw; half >= 1; half /= 2, --bit) {
-                    const bool up = (idx >> bit) & 1u;
-#pragma unroll
-                    for (int w = 0; w < half; ++w) v[w] = up ? v[w + half] : v[w];
-                }
-                uint32_t wsel = v[0];
-                if constexpr (kSplit) {
-                    // ... from the group lane that stored it: lane idx >> (5 + log NDW)
-                    const uint32_t owner = (idx >> (5 + kLogNdw)) & ((1u << LB) - 1);
-                    if constexpr (LB == 1) {
-                        const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 2, 2)>((int)wsel);
-                        const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 3, 3)>((int)wsel);
-                        wsel = owner ? b1 : b0;
-                    } else {
-                        // lane owner & 3 of this quad, then for groups of 8
-                        // the other quad's when owner bit 2 differs from ours
-                        const uint32_t b0 = (uint32_t)dpp_int<quad_sel(0, 0, 0, 0)>((int)wsel);
-                        const uint32_t b1 = (uint32_t)dpp_int<quad_sel(1, 1, 1, 1)>((int)wsel);
-                        const uint32_t b2 = (uint32_t)dpp_int<quad_sel(2, 2, 2, 2)>((int)wsel);
-                        const uint32_t b3 = (uint32_t)dpp_int<quad_sel(3, 3, 3, 3)>((int)wsel);
-                        wsel = owner & 2u ? (owner & 1u ? b3 : b2) : (owner & 1u ? b1 : b0);
-                        if constexpr (LB == 3) {
-                            const uint32_t other = (uint32_t)bit2_flip((int)wsel);
-                            wsel = ((owner >> 2) & 1u) != (uint32_t)((ell >> 2) & 1) ? other : wsel;
-                        }
-                    }
-                }
-                dec = (wsel >> (idx & 31u)) & 1u;
-            }
-            idx = (idx & ~(1u << qpos)) | (dec << qpos);
+            follow(row, sub, (uint32_t)qpos);
         }
         ph = ph == 0 ? V - 1 : ph - 1;
     };
