@@ -107,10 +107,14 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
         // longest first (load balance); PBs that start their traceback from
         // the best state must share a tile with PBs of the same length only,
         // so that all of a tile's final metrics are taken at one stage
+        // (equal geometries next to each other, so that most tiles hold PBs
+        // of one geometry and run the kernel's uniform-wave path)
         std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) {
             const bool ax = x.flags & pbvd::kLaneArgmin, ay = y.flags & pbvd::kLaneArgmin;
             if (ax != ay) return ax < ay;
-            return x.len > y.len;
+            if (x.len != y.len) return x.len > y.len;
+            if (x.store0 != y.store0) return x.store0 < y.store0;
+            return x.dec_end < y.dec_end;
         });
         wl->groups[ci].tile_begin = (int64_t)wl->heads.size();
         size_t i = 0;
@@ -128,7 +132,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             pbvd::TileHead h{};
             h.len = 0;
             h.store0_min = 0x7fffffff;
-            bool wide = true, final_needed = false;
+            bool wide = true, final_needed = false, uniform = true;
             for (size_t k = i; k < i + pw; ++k) {
                 // PBs past the tile's repeat its first PB, inactive; every
                 // lane of a PB's group gets the PB's descriptor
@@ -141,13 +145,15 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 d.dec_end = r.dec_end;
                 d.flags = k < e ? r.flags : (r.flags & ~pbvd::kLaneActive);
                 for (int g = 0; g < (1 << lb); ++g) wl->lanes.push_back(d);
+                if (r.len != v[i].len || r.store0 != v[i].store0 || r.dec_end != v[i].dec_end) uniform = false;
                 if (r.len > h.len) h.len = r.len;
                 if (r.store0 < h.store0_min) h.store0_min = r.store0;
                 const int64_t last_trip = ((r.len - 1) / U) * U;
                 if (r.sym + last_trip * c.R + 4 * ND > sym_bytes) wide = false;
                 if (r.flags & pbvd::kLaneArgmin) final_needed = true;
             }
-            h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0);
+            h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0) |
+                      (uniform ? pbvd::kTileUniform : 0);
             wl->heads.push_back(h);
             i = e;
         }

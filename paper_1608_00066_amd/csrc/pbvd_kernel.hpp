@@ -56,6 +56,12 @@ __device__ __forceinline__ bool static_for(F &&f) {
 #ifndef PBVD_TRACEBACK_BLOCKS
 #define PBVD_TRACEBACK_BLOCKS 3
 #endif
+// VGPRs per lane for the row ring of the phase-aligned traceback (waves with
+// one geometry): its steps are a few dependent ALU operations, so the ring is
+// made as deep as this allows (the path metrics are dead by then).
+#ifndef PBVD_TRACEBACK_RING_VGPRS
+#define PBVD_TRACEBACK_RING_VGPRS 48
+#endif
 
 struct KernelArgs {
     const uint8_t *syms;    // T*R received symbols, stage-major
@@ -888,6 +894,9 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         //      last block (and the one holding the decoded range's end) check
         //      stage bounds. ----
         constexpr int TB = V;
+        constexpr int kRing = PBVD_TRACEBACK_RING_VGPRS / (TB * W) < 2 ? 2
+                            : PBVD_TRACEBACK_RING_VGPRS / (TB * W) > 12 ? 12
+                            : PBVD_TRACEBACK_RING_VGPRS / (TB * W);
         const int i_top = len - 1;
         const int dec_end = j.my_dec_end;  // decoded stages are [i_lo, dec_end)
         // take the input bit of stage i (decoded range) into the output word;
@@ -927,16 +936,16 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
                 tb_rows.load(row, dst[t]);
             }
         };
-        uint32_t ring[kDepth][TB][W];
+        uint32_t ring[kRing][TB][W];
         int top = i_top + (V - 1) - i_top % V;  // the first block's top row (phase V-1)
-        static_for<0, kDepth - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+        static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
             load_rows(ring[decltype(dc)::value], top - decltype(dc)::value * TB);
             return true;
         });
         for (;;) {
-            const bool more = static_for<0, kDepth>([&](auto dc) PBVD_INLINE_LAMBDA {
+            const bool more = static_for<0, kRing>([&](auto dc) PBVD_INLINE_LAMBDA {
                 constexpr int d = decltype(dc)::value;
-                load_rows(ring[(d + kDepth - 1) % kDepth], top - (kDepth - 1) * TB);
+                load_rows(ring[(d + kRing - 1) % kRing], top - (kRing - 1) * TB);
                 const int bot = top - TB + 1;
                 if (top > i_top || bot < i_lo || (top >= dec_end && bot < dec_end))
                     run(std::integral_constant<int, 2>{}, ring[d], top);
@@ -1170,11 +1179,13 @@ struct LaneDesc {
 struct TileHead {
     int32_t len;        // longest lane
     int32_t store0_min; // lowest first-traced stage
-    int32_t flags;      // kTileWide | kTileFinal
+    int32_t flags;      // kTileWide | kTileFinal | kTileUniform
     int32_t pad;
 };
 enum { kLaneKnown = 1, kLaneArgmin = 2, kLaneActive = 4 };
-enum { kTileWide = 1, kTileFinal = 2 };
+// kTileUniform: every lane has the same len, store0 and dec_end, so the tile
+// runs the uniform-wave decode body (phase-aligned traceback)
+enum { kTileWide = 1, kTileFinal = 2, kTileUniform = 4 };
 
 struct TileArgs {
     const uint8_t *syms;
@@ -1227,7 +1238,14 @@ __global__ void __launch_bounds__(256)
     rows.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.sp + wave_local * a.sp_wave_dwords, (short)0,
                                                   (int)(a.sp_wave_dwords * 4), kBufferFlags);
     rows.lane_off = (uint32_t)lane * (LY::NDW * 4);
-    decode_body<C, P, KIND, true, LB>(j, rows);
+    if (tflags & kTileUniform) {
+        j.my_len = j.len;
+        j.my_store0 = j.store0_min;
+        j.my_dec_end = __builtin_amdgcn_readfirstlane(d.dec_end);
+        decode_body<C, P, KIND, false, LB>(j, rows);
+    } else {
+        decode_body<C, P, KIND, true, LB>(j, rows);
+    }
 }
 
 }  // namespace pbvd
