@@ -95,6 +95,19 @@ def test_batch_unterminated_hard_int32_and_small_trellis(torch, pbvd):
     check_batch(torch, pbvd, codes, 120, 1, 700, seed=21)
 
 
+@pytest.mark.parametrize("lanes", [1, 2])
+def test_batch_equal_frames_uniform_tiles(torch, pbvd, lanes):
+    """Frames of one length: whole tiles of PBs with one geometry (interior
+    PBs, and the best-state-start end PBs of unterminated frames), which run
+    the kernel's uniform-wave path, next to the mixed tiles of the frame
+    starts; every frame equals the oracle."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=64, L=42, terminated=False, lanes_per_pb=lanes),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=64, L=54, terminated=False, lanes_per_pb=lanes),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=64, L=42, lanes_per_pb=lanes)]
+    log("batch lanes %d: 150 frames of 1000 bits, K=7 + K=9 unterminated, K=7 r1/3" % lanes)
+    check_batch(torch, pbvd, codes, 150, 1000, 1000, seed=31)
+
+
 def test_batch_graph_capture_replays(torch, pbvd):
     """The decode call only launches kernels: capture it in a HIP graph and
     replay it several times with eager work in between."""
