@@ -370,6 +370,12 @@ def test_workspace_chunking(torch, pbvd, monkeypatch):
     with pbvd.Plan(7, (0o171, 0o133), 512, 42) as plan:
         got = gpu_bits(torch, plan.decode(dsyms, n), n)
     assert np.array_equal(got, ref)
+    # with the stream-end PBs folded into wave 0 of the first launch
+    monkeypatch.setenv("PBVD_FOLD_SIMDS", "1")
+    for lanes in (1, 2):
+        with pbvd.Plan(7, (0o171, 0o133), 512, 42, lanes_per_pb=lanes) as plan:
+            got = gpu_bits(torch, plan.decode(dsyms, n), n)
+        assert np.array_equal(got, ref), "lanes %d" % lanes
 
 
 @pytest.mark.parametrize("lanes", [1, 2])
