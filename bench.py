@@ -204,10 +204,10 @@ def bench_ber_vs_l(torch, log2_bits: int = 24, ebn0s=(2.0, 3.0, 4.0),
     return res
 
 
-def bench_batched(torch, steps: int):
+def bench_batched(torch, steps: int, fixed=None):
     """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
-    50/50, Eb/N0 U[1, 5] dB): D tuned, HIP-graph replay timed, against one
-    plain launch per frame."""
+    50/50, Eb/N0 U[1, 5] dB): D tuned (or `fixed` = (D, lanes per PB)),
+    HIP-graph replay timed, against one plain launch per frame."""
     from paper_1608_00066_amd import autotune, datagen, pbvd
     base = [dict(K=7, gens=(0o171, 0o133), L=42), dict(K=7, gens=(0o133, 0o171, 0o165), L=42)]
     frames, streams, syms_h, out_bytes = datagen.make_frames(
@@ -215,7 +215,10 @@ def bench_batched(torch, steps: int):
     n_bits = sum(f[1] for f in frames)
     syms = torch.from_numpy(syms_h).cuda()
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
-    codes, table = autotune.tune_batch_d(torch, base, frames, syms, out)
+    if fixed:
+        codes, table = [dict(c, D=fixed[0], lanes_per_pb=fixed[1]) for c in base], []
+    else:
+        codes, table = autotune.tune_batch_d(torch, base, frames, syms, out)
     D = codes[0]["D"]
     log("batched: tuned D=%d lanes=%d" % (D, codes[0]["lanes_per_pb"]))
     with pbvd.Batch(codes) as b:
@@ -310,6 +313,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds of Poisson load per arrival rate in the serving measurement")
+    ap.add_argument("--only-batched", type=int, nargs=2, default=None, metavar=("D", "LANES"),
+                    help="only run the batched measurement at block length D and LANES lanes "
+                         "per PB (no tuning), print its JSON and exit (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters of rocprofv3) and exit")
@@ -326,6 +332,9 @@ def main():
     from paper_1608_00066_amd import datagen, pbvd
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_batched:
+        print(json.dumps(bench_batched(torch, args.steps, tuple(args.only_batched))), flush=True)
+        return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
