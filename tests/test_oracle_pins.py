@@ -376,3 +376,81 @@ def test_ber_sanity_k7():
     bound = sum(Bd * 0.5 * math.erfc(math.sqrt(d * r * e)) for d, Bd in B.items())
     assert ber < datagen.uncoded_ber(ebn0)
     assert 0.1 * bound < ber < 3.0 * bound, (ber, bound)
+
+
+def _bruteforce_decisions(K, gens, q, f0, f1, known_start):
+    """Survivor decisions of every (stage, state) of one block by exhaustive
+    search, from the definition of add-compare-select (Eq. 1, ties to the
+    upper branch): at stage s the decision of state j is 1 when the best
+    path reaching j through its lower predecessor 2(j mod 2^(K-2)) + 1 is
+    strictly cheaper than the best one through its upper predecessor.  Every
+    start state is tried; with a known start the states other than 0 begin
+    at 8192 instead of 0 (the same start the decoder defines).
+    Returns dec[s - f0][j]."""
+    R = len(gens)
+    N = 1 << (K - 1)
+    m = f1 - f0
+    nxt, lab = oracle.trellis(K, gens)
+    INF = 1 << 60
+    # via[t][j][0 / 1]: best metric of a path reaching j at the end of stage
+    # f0 + t through the upper / lower predecessor
+    via = [[[INF, INF] for _ in range(N)] for _ in range(m)]
+    for s0 in range(N):
+        start = 0 if (not known_start or s0 == 0) else 8192
+        for u in itertools.product((0, 1), repeat=m):
+            s, metric = s0, start
+            for t, x in enumerate(u):
+                c = lab[s][x]
+                for r in range(R):
+                    bit = (c >> (R - 1 - r)) & 1
+                    qv = int(q[f0 + t][r])
+                    if bit != (qv < 0):
+                        metric += abs(qv)
+                ns = nxt[s][x]
+                side = s & 1  # the lower predecessor of ns is the odd state
+                assert s >> 1 == ns & ((N >> 1) - 1)
+                if metric < via[t][ns][side]:
+                    via[t][ns][side] = metric
+                s = ns
+    return [[1 if via[t][j][1] < via[t][j][0] else 0 for j in range(N)] for t in range(m)]
+
+
+@pytest.mark.parametrize("K,gens,n,D,L,terminated", [
+    (3, (0o7, 0o5), 14, 4, 3, True),
+    (3, (0o5, 0o7, 0o7), 11, 3, 2, False),
+    (4, (0o15, 0o17), 10, 4, 2, True),
+    (4, (0o13, 0o15, 0o17), 9, 3, 2, False),
+])
+def test_survivor_export_bruteforce(K, gens, n, D, L, terminated):
+    """The exported survivor rows ``dec`` (rows s - bD for stages s in
+    [bD, f1), state-indexed, zero beyond f1): every decision equals the
+    exhaustive-search answer, and walking them back from the traceback start
+    reproduces the decoded bits of each block (Alg. 1 Kernel 2)."""
+    R = len(gens)
+    N = 1 << (K - 1)
+    st = datagen.make_stream(K, gens, n, 0.0, seed=300 + 7 * K + n, terminated=terminated)
+    q = st["syms"].view(np.int8).reshape(-1, R)
+    T = st["T"]
+    res = oracle.decode(K, gens, D, L, st["syms"], n, terminated=terminated, want_dec=True,
+                        want_pm=True)
+    dec = res["dec"]
+    nb = oracle.num_blocks(n, D)
+    assert dec.shape == (nb, D + L, N)
+    n_ones = 0
+    for b in range(nb):
+        f0, f1, d0, d1 = oracle.pb_geometry(n, T, D, L, b)
+        ref = _bruteforce_decisions(K, gens, q, f0, f1, known_start=(f0 == 0))
+        for s in range(d0, f1):
+            assert list(dec[b, s - d0]) == ref[s - f0], (b, s)
+            n_ones += sum(ref[s - f0])
+        assert not dec[b, f1 - d0:].any()
+        # the traceback read back from the exported rows
+        fpm = res["final_pm"][b]
+        state = int(np.argmin(fpm)) if (f1 == T and not terminated) else 0
+        bits = []
+        for s in range(f1 - 1, d0 - 1, -1):
+            if s < d1:
+                bits.append((state >> (K - 2)) & 1)
+            state = 2 * (state & ((N >> 1) - 1)) + int(dec[b, s - d0, state])
+        assert bits[::-1] == list(res["bits"][d0:d1]), b
+    assert n_ones > 0  # the noise makes both branches win somewhere
