@@ -84,27 +84,74 @@ def time_decode(torch, plan, syms, n_bits, out, steps, warmup):
     return (t1 - t0) * 1e3 / steps, kernel_ms
 
 
-def cpu_baseline(st, K, gens, D, L, target_s: float):
-    """The CPU oracle on a contiguous sample of the same stream's blocks,
-    using every host core; sample size calibrated to about target_s."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads() -> int:
+    """Threads the oracle may use: the CPUs this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(st, K, gens, D, L, target_s: float, gpu_bits, batch_check=None):
+    """The CPU oracle on a contiguous sample of the same stream's blocks
+    (the whole stream when it fits about target_s), using every host core,
+    plus a single-threaded leg on a smaller sample.  The multi-threaded
+    leg's bits are compared with the GPU's output of the same blocks, and
+    every frame of the batched decode (batch_check) with the oracle."""
+    import numpy as np
+
     import oracle
     n = st["n"]
-    threads = os.cpu_count() or 1
+    threads = host_threads()
     nb_total = oracle.num_blocks(n, D)
-    probe = min(nb_total, max(64, 8 * threads))
-    t0 = time.perf_counter()
-    oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=probe, nthreads=threads)
-    dt = time.perf_counter() - t0
-    count = int(min(nb_total, max(probe, probe * target_s / max(dt, 1e-3))))
+
+    def calibrated(nthreads, budget_s, probe):
+        probe = min(nb_total, probe)
+        t0 = time.perf_counter()
+        oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=probe, nthreads=nthreads)
+        dt = time.perf_counter() - t0
+        return int(min(nb_total, max(probe, probe * budget_s / max(dt, 1e-3))))
+
+    count = calibrated(threads, target_s, max(64, 8 * threads))
     t0 = time.perf_counter()
     res = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=count,
                         nthreads=threads)
     dt = time.perf_counter() - t0
     bits = res["bits"].size
-    return {"value": round(bits / dt / 1e6, 3), "unit": "Mbps", "cores": threads,
-            "kind": "oracle",
-            "sample": "first %d of %d parallel blocks (%d decoded bits) of the same stream, "
-                      "%.1f s" % (count, nb_total, bits, dt)}
+    same = bool(np.array_equal(res["bits"], gpu_bits[:bits]))
+    count1 = calibrated(1, target_s / 2, 64)
+    t0 = time.perf_counter()
+    r1 = oracle.decode(K, gens, D, L, st["syms"], n, pb_first=0, pb_count=count1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    bits1 = r1["bits"].size
+    same = same and bool(np.array_equal(r1["bits"], gpu_bits[:bits1]))
+    cpu = {"value": round(bits / dt / 1e6, 3), "unit": "Mbps", "cores": threads,
+           "kind": "oracle",
+           "sample": "first %d of %d parallel blocks (%d decoded bits) of the same stream, "
+                     "%.1f s on %d threads" % (count, nb_total, bits, dt, threads),
+           "single_thread": {"value": round(bits1 / dt1 / 1e6, 3), "unit": "Mbps", "cores": 1,
+                             "sample": "first %d parallel blocks (%d decoded bits), %.1f s"
+                                       % (count1, bits1, dt1)},
+           "cpu_model": cpu_model()}
+    parity = {"equal": same, "bits_compared": bits,
+              "scope": "GPU output of the timed decode against the oracle, bit for bit, over "
+                       "the first %d of %d parallel blocks" % (count, nb_total)}
+    if batch_check is not None:
+        parity["batched_equal"] = batch_matches_oracle(*batch_check)
+        parity["batched_scope"] = "every frame of the batched decode (%d frames)" % len(batch_check[1])
+    return cpu, parity
 
 
 def plain_per_frame(torch, pbvd, codes, frames, syms, out, reps: int = 1):
@@ -204,6 +251,25 @@ def bench_ber_vs_l(torch, log2_bits: int = 24, ebn0s=(2.0, 3.0, 4.0),
     return res
 
 
+def batch_matches_oracle(codes, frames, streams, host_out) -> bool:
+    """Every frame of a batched decode against the CPU oracle with the same
+    D and L (frames on all host threads; the oracle releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+
+    def ok(f):
+        so, n, oo, ci = frames[f]
+        c = codes[ci]
+        ref = oracle.decode(c["K"], c["gens"], c["D"], c["L"], streams[f]["syms"], n)["bits"]
+        got = np.unpackbits(host_out[oo:oo + (n + 7) // 8], bitorder="little")[:n]
+        return bool(np.array_equal(got, ref))
+    with ThreadPoolExecutor(max_workers=host_threads()) as ex:
+        return all(ex.map(ok, range(len(frames))))
+
+
 def bench_batched(torch, steps: int, fixed=None):
     """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
     50/50, Eb/N0 U[1, 5] dB): D tuned (or `fixed` = (D, lanes per PB)),
@@ -261,10 +327,13 @@ def bench_batched(torch, steps: int, fixed=None):
         "batched_graph_ms": round(wall * 1e3, 4), "batched_event_ms": round(dev * 1e3, 4),
         "batched_mbps": round(n_bits / wall / 1e6, 1),
         "batched_alu_frac": round(ops / dev / PEAK_ALU_OPS[16], 4),
+        "batched_alu_tops": round(ops / dev / 1e12, 3),
         "plain_per_frame_d512_mbps": round(n_bits / t_plain_512 / 1e6, 2),
         "plain_per_frame_same_d_mbps": round(n_bits / t_plain_d / 1e6, 2),
         "speedup_vs_plain_d512": round(t_plain_512 / wall, 1),
         "batched_equals_plain_same_d": same,
+        # for the oracle comparison of the CPU-baseline leg (not printed)
+        "_check": (codes, frames, streams, batched.cpu().numpy()),
         "lanes_per_pb": codes[0]["lanes_per_pb"],
         "tuning_ms": {"D%d_lanes%d" % dl: round(t * 1e3, 4) for dl, t, _ in table},
     }
@@ -301,6 +370,19 @@ def bench_serving(seconds: float, rates=(2000, 5000, 10000, 20000, 50000)):
     return res
 
 
+def batched_summary(b):
+    """The batched leg of the metric next to the plain value: decoded Mbps of
+    the graph-replayed batch, its ALU roofline, and the plain per-frame
+    launches it replaces."""
+    if not b:
+        return None
+    return {"value": b["batched_mbps"], "unit": "Mbps", "ms_per_step": b["batched_graph_ms"],
+            "workload": b["workload"], "D": b["D"],
+            "roofline": {"bound": "alu", "achieved": b["batched_alu_tops"], "peak": PEAK_ALU_OPS[16] / 1e12,
+                         "unit": "Tops/s", "frac": b["batched_alu_frac"]},
+            "plain_per_frame_mbps": b["plain_per_frame_d512_mbps"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -333,7 +415,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only_batched:
-        print(json.dumps(bench_batched(torch, args.steps, tuple(args.only_batched))), flush=True)
+        res = bench_batched(torch, args.steps, tuple(args.only_batched))
+        res.pop("_check", None)
+        print(json.dumps(res), flush=True)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -394,10 +478,13 @@ def main():
         log("serving")
         extras["serving"] = bench_serving(args.serve_seconds)
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        cpu = cpu_baseline(st, K, gens, D, L, args.cpu_seconds)
+        cpu, parity = cpu_baseline(st, K, gens, D, L, args.cpu_seconds, bits,
+                                   extras.get("batched", {}).get("_check"))
+    if "batched" in extras:
+        extras["batched"].pop("_check", None)
 
     rec = {
         "metric": METRIC,
@@ -428,6 +515,8 @@ def main():
             "traffic": measured_traffic(),
         },
         "cpu_baseline": cpu,
+        "parity": parity,
+        "batched": batched_summary(extras.get("batched")),
         "extras": extras,
     }
     plan.close()

@@ -213,10 +213,13 @@ pbvd_status pbvd_batch_create(const pbvd_code *codes, int32_t n_codes, pbvd_batc
  * (PBs of all frames, grouped by code, longest first, 64 per wave), uploads
  * it and sizes the device workspace.  sym_bytes / out_bytes are the sizes of
  * the device buffers later passed to pbvd_batch_decode; every frame must lie
- * inside them and output ranges must not overlap.  Synchronous: waits for
- * all work on the device (earlier decodes of this batch may still read the
- * work list it replaces), then uploads; PBVD_EINVAL on a bad frame (nothing
- * is changed). */
+ * inside them and output ranges must not overlap.  Synchronous: first waits
+ * for this batch's earlier decodes (those launched outside graph capture;
+ * nothing else on the device is waited for), then uploads.  A graph captured
+ * from pbvd_batch_decode refers to the work list of its capture: it must
+ * have finished before, and must not be replayed after, the next call.
+ * PBVD_EINVAL on a bad frame (nothing is changed); after any other failure
+ * the batch holds no frames (decodes write nothing) until a call succeeds. */
 pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64_t n_frames,
                                   int64_t sym_bytes, int64_t out_bytes);
 

@@ -43,10 +43,11 @@ def _run(cmd):
 
 
 def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
-          build_dir: str = BUILD_DIR, lib: str = LIB, defines=()) -> str:
+          build_dir: str = BUILD_DIR, lib: str = LIB, defines=(), incremental: bool = False) -> str:
     """Compile every unit and link ``libpbvd.so``; returns its path.
     ``csrc``/``build_dir``/``lib``/``defines`` let a copy of the sources be
-    built elsewhere with other tuning macros."""
+    built elsewhere with other tuning macros.  ``incremental`` keeps object
+    files newer than every source and header (a full build otherwise)."""
     os.makedirs(build_dir, exist_ok=True)
     jobs = jobs or min(16, os.cpu_count() or 4)
     flags = [f if f.startswith("-") else "-D" + f for f in defines]
@@ -58,8 +59,16 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
     for name in ("pbvd_capi", "pbvd_batch", "pbvd_server", "pbvd_aux"):
         units.append((os.path.join(csrc, name + ".hip"), os.path.join(build_dir, name + ".o"), []))
 
+    # a unit depends on its own source and on every header
+    headers = [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".hpp")]
+    headers.append(os.path.join(INCLUDE, "pbvd.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
+
     def compile_unit(u):
         src, obj, extra = u
+        if (incremental and not defines and os.path.exists(obj)
+                and os.path.getmtime(obj) > max(newest_header, os.path.getmtime(src))):
+            return obj
         _run([HIPCC, *COMMON[:-2], *flags, *extra, "-c", src, "-o", obj])
         if verbose:
             print("built", os.path.basename(obj), flush=True)
@@ -75,5 +84,5 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
 
 
 if __name__ == "__main__":
-    path = build(verbose="-v" in sys.argv)
+    path = build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv)
     print(path)

@@ -214,6 +214,10 @@ struct pbvd_batch {
     hipStream_t aux[kMaxCodes] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kMaxCodes] = {};
+    // recorded on the caller's stream after the last decode launched outside
+    // graph capture (its forked codes joined back first)
+    hipEvent_t done = nullptr;
+    bool done_recorded = false;
 };
 
 namespace {
@@ -229,6 +233,7 @@ void release(pbvd_batch *b) {
         if (b->join[i]) (void)hipEventDestroy(b->join[i]);
     }
     if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->done) (void)hipEventDestroy(b->done);
 }
 
 }  // namespace
@@ -278,16 +283,25 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     if (st != PBVD_OK) return st;
     DeviceGuard dg(b->device);
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", b->device);
-    {
+    if (b->done_recorded) {
         // earlier decodes of this batch may still read the work list and
-        // the survivor area that are replaced below
-        hipError_t e = hipDeviceSynchronize();
+        // the survivor area that are replaced below: wait for them (and for
+        // nothing else on the device)
+        hipError_t e = hipEventSynchronize(b->done);
         if (e != hipSuccess) return fail_hip(e, "waiting for earlier decodes");
+        b->done_recorded = false;
     }
+    // from here on the old work list is gone: a call that fails below leaves
+    // an empty batch (its decodes write nothing) until frames are set again
+    b->n_tiles = 0;
+    b->n_blocks = 0;
+    b->n_stages = 0;
+    for (int ci = 0; ci < kMaxCodes; ++ci) b->groups[ci] = TileGroup{};
     {
         // streams and events of the fork, made once, outside any capture
         hipError_t e = hipSuccess;
         if (!b->fork) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        if (e == hipSuccess && !b->done) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
         for (int i = 1; i < b->cs.n && e == hipSuccess; ++i) {
             if (!b->aux[i]) e = hipStreamCreateWithFlags(&b->aux[i], hipStreamNonBlocking);
             if (e == hipSuccess && !b->join[i]) e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming);
@@ -310,6 +324,8 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
         total += g.n_tiles > 0 ? per_launch[ci] * g.sp_wave_dwords : 0;
     }
     st = ensure_buffer(&b->sp, &b->sp_bytes, (size_t)std::max<int64_t>(total, 64) * 4, "survivors");
+    if (st == PBVD_OK && fault_injected("batch_alloc"))
+        st = fail(PBVD_ENOMEM, "injected allocation failure after the survivor area");
     if (st != PBVD_OK) return st;
     const size_t lb = std::max<size_t>(wl.lanes.size(), 1) * sizeof(pbvd::LaneDesc);
     const size_t hb = std::max<size_t>(wl.heads.size(), 1) * sizeof(pbvd::TileHead);
@@ -375,6 +391,16 @@ pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out,
     for (int k = 1; k < n_active; ++k) {
         hipError_t e = hipStreamWaitEvent(s, b->join[active[k]], 0);
         if (e != hipSuccess) return fail_hip(e, "join wait");
+    }
+    // remember the end of this decode for the next pbvd_batch_set_frames
+    // (not inside a graph capture: a replay's completion is the caller's)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return fail_hip(e, "capture query");
+    if (cap == hipStreamCaptureStatusNone) {
+        e = hipEventRecord(b->done, s);
+        if (e != hipSuccess) return fail_hip(e, "completion event");
+        b->done_recorded = true;
     }
     return PBVD_OK;
 }

@@ -58,28 +58,42 @@ struct Request {
     int32_t batch_frames = 0;
     int32_t status = PBVD_OK;
     bool done = false;
-    // admission footprint
-    int64_t sym_bytes = 0, out_bytes = 0, n_pbs = 0;
+    // admission footprint: all PBs, and those of them that start their
+    // traceback from the best state (the end of an unterminated frame)
+    int64_t sym_bytes = 0, out_bytes = 0, n_pbs = 0, n_argmin_pbs = 0;
 };
 
-// Bytes a set of requests needs in one slot: conservative tile count per code
-// (full waves plus one extra tile per frame whose traceback starts from the
-// best state, since those only share tiles with PBs of equal length).
+// PBs of a frame that start their traceback from the best state: on an
+// unterminated frame, every PB whose forward range reaches the last stage T
+// (bD + D + L >= T); with L >= D there are several.
+int64_t argmin_pbs(const pbvd_code &c, int64_t n_bits) {
+    if (c.terminated) return 0;
+    const int64_t nb = ceil_div(n_bits, c.D);
+    const int64_t T = n_bits;
+    const int64_t lim = T - c.D - c.L;  // b*D >= lim
+    const int64_t first = lim <= 0 ? 0 : ceil_div(lim, c.D);
+    return first >= nb ? 0 : nb - first;
+}
+
+// Bytes a set of requests needs in one slot.  Tile count per code, an upper
+// bound of what build_work_list makes: the other PBs fill whole waves, and
+// every best-state-start PB is counted as a tile of its own (they share
+// tiles only with PBs of the same length).
 struct Footprint {
     int64_t sym = 0, out = 0, frames = 0;
     int64_t pbs[kMaxCodes] = {};
-    int64_t argmin_frames[kMaxCodes] = {};
+    int64_t argmin[kMaxCodes] = {};
 
-    void add(const Request &r, const CodeSet &cs) {
+    void add(const Request &r, const CodeSet &) {
         sym += r.sym_bytes;
         out += r.out_bytes;
         frames += 1;
-        pbs[r.code] += r.n_pbs;
-        if (!cs.codes[r.code].terminated) argmin_frames[r.code] += 1;
+        pbs[r.code] += r.n_pbs - r.n_argmin_pbs;
+        argmin[r.code] += r.n_argmin_pbs;
     }
     // lb[] of the code set: 64 >> lb PBs per tile
     int64_t tiles(int ci, const CodeSet &cs) const {
-        return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + argmin_frames[ci];
+        return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + argmin[ci];
     }
     int64_t lanes_bytes(const CodeSet &cs) const {
         int64_t t = 0;
@@ -441,6 +455,7 @@ pbvd_status pbvd_server_submit(pbvd_server *sv, int32_t code, const void *syms, 
         r->sym_bytes = (n_bits + (c.terminated ? c.K - 1 : 0)) * c.R;
         r->out_bytes = ceil_div(n_bits, 8);
         r->n_pbs = ceil_div(n_bits, c.D);
+        r->n_argmin_pbs = argmin_pbs(c, n_bits);
         Footprint alone;
         alone.add(*r, sv->cs);
         if (alone.device_bytes(sv->cs) > sv->slot_bytes || alone.in_bytes(sv->cs) > sv->pin_in_bytes ||

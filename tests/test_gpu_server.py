@@ -117,3 +117,28 @@ def test_server_unterminated_hard_int32_mix(pbvd):
     for (ci, st), (out, _) in zip(reqs, res):
         assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st)), \
             "request of %d bits (code %d) differs from the oracle" % (st["n"], ci)
+
+
+def test_server_admission_counts_every_best_state_block(pbvd):
+    """Unterminated frames with L > D end in several PBs that start their
+    traceback from the best state (each a tile of its own unless another
+    frame's PB has its length).  A slot budget that fits a few dozen such
+    frames: admission must count those tiles, so every request decodes
+    (none fails with its batch for want of survivor memory) and equals the
+    oracle."""
+    codes = [dict(K=9, gens=(0o557, 0o663, 0o711), D=16, L=54, terminated=False)]
+    rng = np.random.default_rng(505)
+    reqs = []
+    for i in range(120):
+        n = int(rng.integers(150, 450))
+        reqs.append((0, datagen.make_stream(9, codes[0]["gens"], n, float(rng.uniform(1, 5)),
+                                            seed=6000 + i, terminated=False)))
+    log("server: 120 unterminated K=9 frames, D=16 L=54, 3 MiB per batch")
+    with pbvd.Server(codes, device_bytes=6 << 20, max_inflight=2, max_batch_frames=4096) as srv:
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        res = [srv.wait(t) for t in tickets]
+        cnt = srv.counters()
+        log("counters %s" % cnt)
+    assert max(i["batch_frames"] for _, i in res) > 8
+    for (ci, st), (out, _) in zip(reqs, res):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st))

@@ -1,15 +1,20 @@
-"""The 16-byte survivor-row stores keep their data VGPRs untouched for a
-while after they issue.
+"""The 12- and 16-byte survivor-row stores keep their data VGPRs untouched
+for the wait states the hardware needs after they issue.
 
-The vector memory unit reads the data registers of a 128-bit buffer store
-over several cycles after the store issues; a vector instruction that
-overwrites them right away makes the lanes read last (lanes 12-15 of every
-16-lane row) store the new values.  This was measured on MI355X with a
-row layout whose stores were followed at once by such a write, and every
-parity test caught it.  The decoder's 16-byte row stores (codes with four or
-more survivor dwords per lane and row) rely on the compiler not doing that,
-so this test disassembles the built code objects (the library's own build)
-and checks every 16- and 12-byte store."""
+The vector memory unit reads the data registers of a store of more than
+8 bytes after the store issues; on this GPU family an instruction that
+writes them needs two wait states after the store (two other instructions
+or an s_nop in between; the compiler's hazard recognizer inserts that much
+for the stores it schedules).  A write of them at once was measured on
+MI355X with a row layout whose stores were followed directly by such a
+write: the lanes read last (lanes 12-15 of every 16-lane row) stored the new
+values, and every parity test caught it.  The decoder's 16-byte row stores
+(codes with four or more survivor dwords per lane and row) rely on the
+compiler keeping that distance, so this test disassembles the built code
+objects (the library's own build) and searches every path after every
+12- and 16-byte store -- fall-through, taken branches and loop back-edges --
+for an instruction that writes one of its data VGPRs (vector ALU results,
+vector-memory and LDS loads, returning atomics) too early."""
 import glob
 import os
 import re
@@ -21,7 +26,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BUILD = os.path.join(ROOT, "paper_1608_00066_amd", "_build")
 LLVM = "/opt/rocm/llvm/bin"
-MIN_DISTANCE = 8  # instructions between the store and a write of its data
+MIN_DISTANCE = 3  # a write of the store data must be at least this many instructions later
 
 
 def _regs(tok):
@@ -47,25 +52,89 @@ def _disassemble(obj, tmp):
     return r.stdout
 
 
+_INSN = re.compile(r"^\s*([a-z_0-9]+)(?:\s+([^/]*?))?\s*//\s*([0-9A-Fa-f]+):")
+_FUNC = re.compile(r"^([0-9a-f]+) <([^>]+)>:$")
+_TARGET = re.compile(r"<([^>+]+)\+0x([0-9a-f]+)>\s*$")
+
+
+def _parse(text):
+    """Instructions of a disassembly: (mnemonic, operands, branch target
+    index or None), in address order, and the index of each address."""
+    funcs, insns, at = {}, [], {}
+    raw = []
+    for line in text.split("\n"):
+        m = _FUNC.match(line.strip())
+        if m:
+            funcs[m.group(2)] = int(m.group(1), 16)
+            continue
+        m = _INSN.match(line)
+        if not m:
+            continue
+        addr = int(m.group(3), 16)
+        tgt = None
+        if m.group(1).startswith(("s_branch", "s_cbranch")):
+            t = _TARGET.search(line)
+            if t:
+                tgt = (t.group(1), int(t.group(2), 16))
+        at[addr] = len(raw)
+        raw.append((m.group(1), m.group(2) or "", tgt))
+    for mn, ops, tgt in raw:
+        ti = None
+        if tgt and tgt[0] in funcs:
+            ti = at.get(funcs[tgt[0]] + tgt[1])
+        insns.append((mn, ops, ti))
+    return insns
+
+
+def _writes_vgprs(mn, ops):
+    """VGPRs an instruction writes: the destination operand of vector ALU
+    instructions and of loads (vector memory, LDS) and returning atomics."""
+    if not ops:
+        return set()
+    returns = mn.startswith("v_") or "_load" in mn or mn.startswith("ds_read") or \
+        mn.startswith("ds_bpermute") or mn.startswith("ds_permute") or \
+        ("atomic" in mn and re.search(r"\b(glc|sc0)\b", ops) is not None)
+    if not returns:
+        return set()
+    return _regs(ops.split(",")[0])
+
+
 def _violations(text):
-    lines = [l.split("//")[0].strip() for l in text.split("\n")]
+    """Every path of fewer than MIN_DISTANCE instructions after a 12- or
+    16-byte buffer store (fall-through and branch targets, loop back-edges
+    included) is searched for an instruction that writes one of the
+    store's data VGPRs."""
+    insns = _parse(text)
     bad, n_stores = [], 0
-    for i, l in enumerate(lines):
-        if not (l.startswith("buffer_store_dwordx4") or l.startswith("buffer_store_dwordx3")):
+    for i, (mn, ops, _) in enumerate(insns):
+        if mn not in ("buffer_store_dwordx4", "buffer_store_dwordx3"):
             continue
         n_stores += 1
-        data = _regs(l.split(None, 1)[1].split(",")[0])
-        n = 0
-        for t in lines[i + 1:i + 200]:
-            if not t:
-                continue
-            if t.endswith(":") or t.startswith(("s_cbranch", "s_branch", "s_endpgm", "s_setpc")):
-                break
-            n += 1
-            if n >= MIN_DISTANCE:
-                break
-            if t.startswith("v_") and " " in t and _regs(t.split(None, 1)[1].split(",")[0]) & data:
-                bad.append((l, t, n))
+        data = _regs(ops.split(",")[0])
+        # depth-first over successors; seen[(index)] = fewest steps to reach it
+        stack, seen = [(i, 0)], {}
+        while stack:
+            k, n = stack.pop()
+            mk, _, tk = insns[k]
+            succ = []
+            if not mk.startswith(("s_branch", "s_endpgm", "s_setpc")):
+                succ.append(k + 1)
+            if tk is not None:
+                succ.append(tk)
+            for j in succ:
+                if j >= len(insns):
+                    continue
+                nj = n + 1
+                if nj >= MIN_DISTANCE or seen.get(j, MIN_DISTANCE + 1) <= nj:
+                    continue
+                seen[j] = nj
+                mj, oj, _ = insns[j]
+                if _writes_vgprs(mj, oj) & data:
+                    bad.append((mn + " " + ops, mj + " " + oj, nj))
+                    stack.clear()
+                    break
+                stack.append((j, nj))
+            if bad and bad[-1][0] == mn + " " + ops:
                 break
     return bad, n_stores
 
