@@ -75,6 +75,20 @@ enum {
     PBVD_HARD_U8 = 1    /* uint8 per code symbol, bit = byte & 1 */
 };
 
+/* How a PB's trellis (Sec. III-B) is spread over GPU lanes (Sec. IV-A).
+ *   PBVD_MAP_LANES: the register kernel; all 2^(K-1) path metrics of a PB in
+ *     the registers of lanes_per_pb lanes (1, 2, 4, 8), the code compiled in
+ *     (the generator sets of the library's registry); the fastest mapping for
+ *     long streams and large batches.
+ *   PBVD_MAP_WAVE: the state-parallel kernel; one wave per PB, one lane per
+ *     state (two or four for K = 8, 9), metrics exchanged between lanes every
+ *     stage, generators taken at run time: any code of the ranges below, and
+ *     the lowest latency per PB (short streams, single frames).
+ *   PBVD_MAP_AUTO: the wave kernel for codes outside the registry and for
+ *     calls with few PBs, the register kernel otherwise.
+ * Every mapping gives the same bits and metrics. */
+enum { PBVD_MAP_AUTO = 0, PBVD_MAP_LANES = 1, PBVD_MAP_WAVE = 2 };
+
 /* Code and block parameters (Sec. III-A, Sec. III-B). */
 typedef struct {
     int32_t K;          /* constraint length, 3..9 (N = 2^(K-1) states) */
@@ -88,36 +102,50 @@ typedef struct {
     int32_t pm_bits;    /* path-metric width, 16 or 32 (32 needs K <= 8);
                            results are identical, only the kernel differs */
     int32_t lanes_per_pb; /* GPU lanes sharing one PB's trellis: 1, 2, 4 or
-                           8, or 0 to let the library choose per call.  2, 4
-                           and 8 need pm_bits = 16 and K >= 7 (2), K >= 8 (4)
-                           or K = 9 (8).  More lanes per PB cut a PB's latency
-                           and let short streams fill more of the GPU; results
-                           are identical, only the kernel differs */
+                           8 (the register kernel), 64 (a whole wave, one lane
+                           per state: the state-parallel kernel), or 0 to let
+                           the library choose per call.  2, 4 and 8 need
+                           pm_bits = 16 and K >= 7 (2), K >= 8 (4) or K = 9
+                           (8).  More lanes per PB cut a PB's latency and let
+                           short streams fill more of the GPU; results are
+                           identical, only the kernel differs */
+    int32_t mapping;    /* PBVD_MAP_AUTO, PBVD_MAP_LANES or PBVD_MAP_WAVE */
 } pbvd_code;
 
-/* Validate `code`, build the trellis tables and pick the kernel.
- * *out receives a new plan (no device memory is allocated yet).
- * Returns PBVD_EINVAL for out-of-range fields, PBVD_ENOTSUP when no kernel
- * is compiled for this generator set / metric width. */
+/* Validate `code` (the code of Eq. 2 and the blocks of Sec. III-A) and pick
+ * the kernels.  *out receives a new plan (no device memory is allocated yet).
+ * Any generator set within the ranges above decodes (the wave mapping takes
+ * the generators at run time); PBVD_ENOTSUP when the register kernel is
+ * asked for (PBVD_MAP_LANES, or lanes_per_pb of 1..8) and no register
+ * kernel is compiled for this generator set, or for a metric width it does
+ * not support.  PBVD_EINVAL for out-of-range fields (callers must zero
+ * fields they do not set, e.g. mapping). */
 pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out);
 
-/* Decode a whole stream.
+/* Decode a whole stream: the problem of Sec. II solved by the parallel
+ * blocks of Sec. III-A (Fig. 2), each a forward pass (Eq. 1) and a traceback
+ * (Alg. 1, Kernel 2).
  *   d_syms     : device, (n_bits + terminated*(K-1)) * R bytes, stage-major
  *   n_bits     : information bits, >= 1
  *   d_out_bits : device, ceil(n_bits/8) bytes, written completely
  *   hip_stream : hipStream_t or NULL
- * Asynchronous; equivalent to pbvd_decode_ex over all PBs. */
+ * Asynchronous; equivalent to pbvd_decode_ex over all PBs.  Errors as for
+ * pbvd_decode_ex. */
 pbvd_status pbvd_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, uint8_t *d_out_bits,
                         void *hip_stream);
 
 /* Decode PBs [pb_first, pb_first + pb_count) of a stream of n_bits bits
- * (resume, sharding, verification).
+ * (resume, sharding, verification): the PBs of Sec. III-A are independent,
+ * so any sub-range decodes to the same bits as inside the whole stream.
  *   d_out_bits : device, receives decoded bits [pb_first*D, min(n, (pb_first
  *                + pb_count)*D)) of the stream starting at its bit 0;
  *                ceil(that count / 8) bytes, written completely
  *   d_final_pm : device int32 [pb_count][2^(K-1)] or NULL: path metrics at the
  *                end of each PB's forward range minus their minimum
- * pb_count may be 0 (nothing is written).  Asynchronous. */
+ * pb_count may be 0 (nothing is written).  Asynchronous.  PBVD_EINVAL for a
+ * NULL plan or buffer, n_bits < 1 or a PB range outside [0, ceil(n_bits/D));
+ * PBVD_ENOMEM when the plan's survivor workspace cannot grow; PBVD_EHIP on a
+ * launch failure.  On an error nothing has been written. */
 pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
                            int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
                            void *hip_stream);
@@ -143,11 +171,14 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
 pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
                              int32_t n_streams, int64_t chunk_pbs, uint32_t flags);
 
-/* Lanes per PB (1, 2, 4 or 8) that pbvd_decode_ex of PBs [pb_first, pb_first +
- * pb_count) of an n_bits-bit stream uses: the plan's lanes_per_pb, or with 0
- * the library's choice: one lane for K <= 7 when that gives 4096 waves of 64
- * PBs, else pairs of lanes where the code allows them when that gives 1024
- * waves, else the largest group the code allows.  0 on invalid arguments. */
+/* Lanes per PB (1, 2, 4, 8, or 64 for the wave mapping) that pbvd_decode_ex
+ * of PBs [pb_first, pb_first + pb_count) of an n_bits-bit stream uses: the
+ * plan's mapping and lanes_per_pb, or the library's choice: the wave
+ * mapping for codes outside the registry and for calls of fewer PBs than a
+ * threshold (PBVD_WAVE_MAX_PBS overrides it); else one lane for K <= 7 when
+ * that gives 4096 waves of 64 PBs, else pairs of lanes where the code allows
+ * them when that gives 1024 waves, else the largest group the code allows.
+ * 0 on invalid arguments. */
 int32_t pbvd_call_lanes(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count);
 
 /* Number of parallel blocks of a stream: ceil(n_bits / D); 0 if n_bits < 1. */

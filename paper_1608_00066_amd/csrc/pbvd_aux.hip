@@ -6,6 +6,7 @@
 
 #include "pbvd_aux.hpp"
 #include "pbvd_kernel.hpp"
+#include "pbvd_wave.hpp"
 
 namespace pbvd {
 namespace {
@@ -72,6 +73,40 @@ __global__ void unpack_survivors_kernel(SurvivorView v, uint8_t *dec) {
     }
 }
 
+// The same for the state-parallel kernel: PB p of the call in slot p; its
+// trips are aligned to the end of its forward range; the decision of state
+// j at stage i (k-th step of its trip, phase k mod V) sits at position
+// rotl^(k+1)(j): lane u mod 64, slot u / 64, bit W-1-k of the trip's word.
+__global__ void unpack_wave_survivors_kernel(SurvivorView v, uint8_t *dec) {
+    const int V = v.K - 1, N = 1 << V;
+    const int W = wave::trip_stages(V), SL = wave::slots(V);
+    const int64_t rows = (int64_t)v.D + v.L;
+    const int64_t total = v.pb_count * rows * N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int state = (int)(t % N);
+        const int64_t row = (t / N) % rows;
+        const int64_t pbl = t / (N * rows);
+        const int64_t b = v.pb_first + pbl;
+        const int64_t d0 = b * v.D;
+        const int64_t f0 = d0 - v.L < 0 ? 0 : d0 - v.L;
+        const int64_t f1 = d0 + v.D + v.L > v.T ? v.T : d0 + v.D + v.L;
+        uint8_t bit = 0;
+        if (d0 + row < f1) {
+            const int64_t len = f1 - f0;
+            const int64_t n_trips = (len + W - 1) / W;
+            const int64_t kk = (d0 + row - f0) + (n_trips * W - len);
+            const int64_t trip = kk / W;
+            const int k = (int)(kk % W);
+            const int u = rotl_dyn(state, k % V + 1, V);
+            const int lane = u & 63, slot = u >> 6;
+            const uint32_t w = v.sp[pbl * v.sp_wave_dwords + (trip * SL + slot) * kWave + lane];
+            bit = (uint8_t)((w >> (W - 1 - k)) & 1u);
+        }
+        dec[t] = bit;
+    }
+}
+
 template <int R, int KIND>
 __global__ void branch_metrics_kernel(const uint8_t *syms, int64_t n_stages, int32_t *out) {
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_stages;
@@ -119,7 +154,10 @@ hipError_t words_to_bytes(const uint32_t *w, uint8_t *out, int64_t nbytes, hipSt
 hipError_t unpack_survivors(const SurvivorView &v, uint8_t *dec, hipStream_t s) {
     const int64_t total = v.pb_count * ((int64_t)v.D + v.L) * (1 << (v.K - 1));
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(unpack_survivors_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, v, dec);
+    if (v.wave)
+        hipLaunchKernelGGL(unpack_wave_survivors_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, v, dec);
+    else
+        hipLaunchKernelGGL(unpack_survivors_kernel, dim3(grid_for(total, 256)), dim3(256), 0, s, v, dec);
     return hipGetLastError();
 }
 

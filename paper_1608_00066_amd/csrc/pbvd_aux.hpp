@@ -15,6 +15,8 @@ struct SurvivorView {
     int32_t K, D, L;
     int32_t byte_perm;  // survivor bit layout: 1 = byte-permute, 0 = shift
     int32_t lb;         // 2^lb lanes per PB (64 >> lb PBs per wave)
+    int32_t wave;       // 1: the state-parallel kernel's layout (one PB per
+                        // slot of sp_wave_dwords, [trip][slot][lane] words)
 };
 
 hipError_t fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t s);

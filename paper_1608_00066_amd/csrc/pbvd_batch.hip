@@ -31,7 +31,7 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
         cs.idx[i] = idx;
         const int req = requested_lb(codes[i]);
         const int top = max_lb(codes[i]);
-        cs.lb[i] = req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
+        cs.lb[i] = idx < 0 ? kWaveLb : req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
     }
     cs.n = n;
     *out = cs;
@@ -97,11 +97,24 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
 
     wl->lanes.clear();
     wl->heads.clear();
+    wl->descs.clear();
     for (int ci = 0; ci < cs.n; ++ci) {
         const pbvd_code &c = cs.codes[ci];
         const int64_t U = pbvd::trip_stages(c.K);
         const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
         const int lb = cs.lb[ci];
+        if (lb == kWaveLb) {
+            // one wave per PB, longest first
+            std::vector<PbRec> &v = per_code[ci];
+            std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) { return x.len > y.len; });
+            wl->groups[ci].tile_begin = (int64_t)wl->descs.size();
+            for (const PbRec &r : v)
+                wl->descs.push_back(pbvd::LaneDesc{r.sym, r.out_bit, r.len, r.store0, r.dec_end, r.flags});
+            wl->groups[ci].n_tiles = (int64_t)v.size();
+            wl->groups[ci].sp_wave_dwords = wave_slot_dwords(c);
+            wl->groups[ci].lb = lb;
+            continue;
+        }
         const size_t pw = (size_t)(pbvd::kWave >> lb);  // PBs per tile
         std::vector<PbRec> &v = per_code[ci];
         // longest first (load balance); PBs that start their traceback from
@@ -166,8 +179,33 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
 
 pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const uint8_t *d_syms,
                          int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
-                         const pbvd::TileHead *d_heads, uint32_t *sp, int64_t per_launch,
-                         hipStream_t stream) {
+                         const pbvd::TileHead *d_heads, const pbvd::LaneDesc *d_descs, uint32_t *sp,
+                         int64_t per_launch, hipStream_t stream) {
+    if (g.lb == kWaveLb) {
+        const pbvd_code &c = cs.codes[ci];
+        pbvd::WaveLaunchRequest req{};
+        pbvd::wave::Args &a = req.args;
+        a.syms = d_syms;
+        a.in_end = d_syms + sym_bytes;
+        a.out = d_out;
+        a.out_mode = pbvd::kOutBytes;
+        a.sp = sp;
+        a.sp_wave_dwords = g.sp_wave_dwords;
+        a.descs = d_descs + g.tile_begin;
+        for (int r = 0; r < 4; ++r) a.gen[r] = r < c.R ? c.gen[r] : 0u;
+        req.R = c.R;
+        req.input_kind = c.input_kind;
+        req.stream = stream;
+        const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
+        for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
+            a.wave_begin = t0;
+            a.n_waves = std::min(per_launch, g.n_tiles - t0);
+            req.grid = (unsigned)ceil_div(a.n_waves, waves_per_block);
+            hipError_t e = launch_wave(c.K, req);
+            if (e != hipSuccess) return fail_hip(e, "batch wave kernel launch");
+        }
+        return PBVD_OK;
+    }
     const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
     for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
         pbvd::TileLaunchRequest req{};
@@ -206,7 +244,8 @@ struct pbvd_batch {
     int64_t sym_bytes = 0, out_bytes = 0;
     pbvd::LaneDesc *d_lanes = nullptr;
     pbvd::TileHead *d_heads = nullptr;
-    size_t lanes_bytes = 0, heads_bytes = 0;
+    pbvd::LaneDesc *d_descs = nullptr;
+    size_t lanes_bytes = 0, heads_bytes = 0, descs_bytes = 0;
     uint32_t *sp = nullptr;
     size_t sp_bytes = 0;
     // codes after the first run on these streams, forked from and joined to
@@ -224,10 +263,11 @@ namespace {
 
 void release(pbvd_batch *b) {
     DeviceGuard dg(b->device);
-    if (b->sp || b->d_lanes || b->d_heads) (void)hipDeviceSynchronize();
+    if (b->sp || b->d_lanes || b->d_heads || b->d_descs) (void)hipDeviceSynchronize();
     if (b->sp) (void)hipFree(b->sp);
     if (b->d_lanes) (void)hipFree(b->d_lanes);
     if (b->d_heads) (void)hipFree(b->d_heads);
+    if (b->d_descs) (void)hipFree(b->d_descs);
     for (int i = 0; i < kMaxCodes; ++i) {
         if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
         if (b->join[i]) (void)hipEventDestroy(b->join[i]);
@@ -270,7 +310,7 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
             if (frames[f].code >= 0 && frames[f].code < cs.n && frames[f].n_bits > 0)
                 pbs[frames[f].code] += ceil_div(frames[f].n_bits, cs.codes[frames[f].code].D);
         for (int ci = 0; ci < cs.n; ++ci)
-            if (requested_lb(cs.codes[ci]) < 0)
+            if (requested_lb(cs.codes[ci]) < 0 && cs.idx[ci] >= 0)
                 cs.lb[ci] = ceil_div(pbs[ci], pbvd::kWave) >= 1024 ? 0 : max_lb(cs.codes[ci]);
     }
     WorkList wl;
@@ -333,6 +373,9 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     if (st != PBVD_OK) return st;
     st = ensure_buffer(reinterpret_cast<uint32_t **>(&b->d_heads), &b->heads_bytes, hb, "work list");
     if (st != PBVD_OK) return st;
+    const size_t db = std::max<size_t>(wl.descs.size(), 1) * sizeof(pbvd::LaneDesc);
+    st = ensure_buffer(reinterpret_cast<uint32_t **>(&b->d_descs), &b->descs_bytes, db, "work list");
+    if (st != PBVD_OK) return st;
     if (!wl.lanes.empty()) {
         hipError_t e = hipMemcpy(b->d_lanes, wl.lanes.data(), wl.lanes.size() * sizeof(pbvd::LaneDesc),
                                  hipMemcpyHostToDevice);
@@ -341,13 +384,18 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
                           hipMemcpyHostToDevice);
         if (e != hipSuccess) return fail_hip(e, "work-list upload");
     }
+    if (!wl.descs.empty()) {
+        hipError_t e = hipMemcpy(b->d_descs, wl.descs.data(), wl.descs.size() * sizeof(pbvd::LaneDesc),
+                                 hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail_hip(e, "work-list upload");
+    }
     b->cs = cs;
     for (int ci = 0; ci < b->cs.n; ++ci) {
         b->groups[ci] = wl.groups[ci];
         b->per_launch[ci] = per_launch[ci];
         b->sp_off[ci] = sp_off[ci];
     }
-    b->n_tiles = (int64_t)wl.heads.size();
+    b->n_tiles = (int64_t)(wl.heads.size() + wl.descs.size());
     b->n_blocks = wl.n_blocks;
     b->n_stages = wl.n_stages;
     b->sym_bytes = sym_bytes;
@@ -378,7 +426,7 @@ pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out,
         hipError_t e = hipStreamWaitEvent(b->aux[ci], b->fork, 0);
         if (e != hipSuccess) return fail_hip(e, "fork wait");
         pbvd_status st = launch_group(b->cs, ci, b->groups[ci], (const uint8_t *)d_syms, b->sym_bytes,
-                                      d_out, b->d_lanes, b->d_heads, b->sp + b->sp_off[ci],
+                                      d_out, b->d_lanes, b->d_heads, b->d_descs, b->sp + b->sp_off[ci],
                                       b->per_launch[ci], b->aux[ci]);
         if (st != PBVD_OK) return st;
         e = hipEventRecord(b->join[ci], b->aux[ci]);
@@ -386,7 +434,7 @@ pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out,
     }
     const int c0 = active[0];
     pbvd_status st = launch_group(b->cs, c0, b->groups[c0], (const uint8_t *)d_syms, b->sym_bytes, d_out,
-                                  b->d_lanes, b->d_heads, b->sp + b->sp_off[c0], b->per_launch[c0], s);
+                                  b->d_lanes, b->d_heads, b->d_descs, b->sp + b->sp_off[c0], b->per_launch[c0], s);
     if (st != PBVD_OK) return st;
     for (int k = 1; k < n_active; ++k) {
         hipError_t e = hipStreamWaitEvent(s, b->join[active[k]], 0);
@@ -411,7 +459,7 @@ pbvd_status pbvd_batch_info(const pbvd_batch *b, int64_t *n_tiles, int64_t *n_bl
     if (n_tiles) *n_tiles = b->n_tiles;
     if (n_blocks) *n_blocks = b->n_blocks;
     if (n_forward_stages) *n_forward_stages = b->n_stages;
-    if (workspace_bytes) *workspace_bytes = (int64_t)(b->sp_bytes + b->lanes_bytes + b->heads_bytes);
+    if (workspace_bytes) *workspace_bytes = (int64_t)(b->sp_bytes + b->lanes_bytes + b->heads_bytes + b->descs_bytes);
     return PBVD_OK;
 }
 

@@ -26,6 +26,10 @@ using LaunchFn = hipError_t (*)(const pbvd::LaunchRequest &);
 #define PBVD_FN(i, K, R, g0, g1, g2, g3) &pbvd::launch_code<i>,
 const LaunchFn kLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_FN)};
 #undef PBVD_FN
+using WaveLaunchFn = hipError_t (*)(const pbvd::WaveLaunchRequest &);
+const WaveLaunchFn kWaveLaunchTable[7] = {&pbvd::launch_wave<3>, &pbvd::launch_wave<4>, &pbvd::launch_wave<5>,
+                                          &pbvd::launch_wave<6>, &pbvd::launch_wave<7>, &pbvd::launch_wave<8>,
+                                          &pbvd::launch_wave<9>};
 using TileLaunchFn = hipError_t (*)(const pbvd::TileLaunchRequest &);
 #define PBVD_TFN(i, K, R, g0, g1, g2, g3) &pbvd::launch_tiles<i>,
 const TileLaunchFn kTileLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_TFN)};
@@ -107,7 +111,17 @@ int64_t slot_dwords(const pbvd_code &c, int lb) {
 }
 
 int requested_lb(const pbvd_code &c) {
+    if (c.mapping == PBVD_MAP_WAVE || c.lanes_per_pb == 64) return kWaveLb;
     return c.lanes_per_pb == 8 ? 3 : c.lanes_per_pb == 4 ? 2 : c.lanes_per_pb == 2 ? 1 : c.lanes_per_pb == 1 ? 0 : -1;
+}
+
+int64_t wave_slot_dwords(const pbvd_code &c) {
+    return ceil_div(pbvd::wave::pb_dwords(c.K - 1, (int64_t)c.D + 2 * (int64_t)c.L), 64) * 64;
+}
+
+hipError_t launch_wave(int K, const pbvd::WaveLaunchRequest &req) {
+    if (K < 3 || K > 9) return hipErrorInvalidValue;
+    return kWaveLaunchTable[K - 3](req);
 }
 
 int max_lb(const pbvd_code &c) {
@@ -143,14 +157,40 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
     if (c.input_kind != PBVD_SOFT_I8 && c.input_kind != PBVD_HARD_U8)
         return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
     if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
-    if (c.pm_bits == 32 && c.K > 8) return fail(PBVD_ENOTSUP, "32-bit path metrics need K <= 8");
+    if (c.mapping != PBVD_MAP_AUTO && c.mapping != PBVD_MAP_LANES && c.mapping != PBVD_MAP_WAVE)
+        return fail(PBVD_EINVAL, "mapping must be PBVD_MAP_AUTO, PBVD_MAP_LANES or PBVD_MAP_WAVE (got %d)",
+                    c.mapping);
     if (c.lanes_per_pb != 0 && c.lanes_per_pb != 1 && c.lanes_per_pb != 2 && c.lanes_per_pb != 4 &&
-        c.lanes_per_pb != 8)
-        return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2, 4 or 8 (got %d)", c.lanes_per_pb);
+        c.lanes_per_pb != 8 && c.lanes_per_pb != 64)
+        return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2, 4, 8 or 64 (got %d)", c.lanes_per_pb);
+    const bool wave_only = c.mapping == PBVD_MAP_WAVE || c.lanes_per_pb == 64;
+    if (c.mapping == PBVD_MAP_WAVE && c.lanes_per_pb != 0 && c.lanes_per_pb != 64)
+        return fail(PBVD_EINVAL, "the wave mapping uses 64 lanes per PB (lanes_per_pb %d)", c.lanes_per_pb);
+    if (c.mapping == PBVD_MAP_LANES && c.lanes_per_pb == 64)
+        return fail(PBVD_EINVAL, "the register mapping uses 1, 2, 4 or 8 lanes per PB, not 64");
+    {
+        // survivor words of one PB of the wave kernel use 32-bit offsets
+        const int64_t slot = wave_slot_dwords(c) * 4;
+        if (slot >= (1LL << 31) - 4096)
+            return fail(PBVD_ENOTSUP, "D + 2L too large for the survivor buffer of one PB (%lld bytes)",
+                        (long long)slot);
+    }
+    const int idx = find_code(c);
+    if (wave_only) {
+        *idx_out = -1;
+        return PBVD_OK;
+    }
+    // the register kernel: compiled generator sets, 32-bit metrics up to K = 8
+    const bool want_lanes = c.mapping == PBVD_MAP_LANES || c.lanes_per_pb != 0;
+    const bool lanes_ok = idx >= 0 && !(c.pm_bits == 32 && c.K > 8);
+    if (!lanes_ok && want_lanes)
+        return fail(PBVD_ENOTSUP, idx < 0 ? "no register kernel compiled for this generator set "
+                                            "(PBVD_MAP_WAVE or PBVD_MAP_AUTO decode any code)"
+                                          : "the register kernel's 32-bit path metrics need K <= 8");
     if (c.lanes_per_pb > 1 && !pbvd::lanes_allowed(c.K, c.pm_bits, requested_lb(c)))
         return fail(PBVD_ENOTSUP, "%d lanes per PB need 16-bit metrics and K >= %d", c.lanes_per_pb,
                     c.lanes_per_pb == 2 ? 7 : c.lanes_per_pb == 4 ? 8 : 9);
-    {
+    if (lanes_ok) {
         // survivor rows of one wave slot are addressed with 32-bit offsets
         const int64_t row_bytes = 64LL * pbvd::survivor_row_dwords(c.K) * 4;
         const int64_t slot =
@@ -159,9 +199,7 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
             return fail(PBVD_ENOTSUP, "D + 2L too large for the survivor buffer of one wave (%lld bytes)",
                         (long long)slot);
     }
-    const int idx = find_code(c);
-    if (idx < 0) return fail(PBVD_ENOTSUP, "no kernel compiled for this generator set");
-    *idx_out = idx;
+    *idx_out = lanes_ok ? idx : -1;
     return PBVD_OK;
 }
 
@@ -304,7 +342,8 @@ struct PipeStream {
 
 struct pbvd_plan {
     pbvd_code code;
-    int code_idx;
+    int code_idx;             // register kernel's registry index, -1: none
+    int64_t wave_max_pbs;     // auto mapping: the wave kernel up to this many PBs
     int device;
     int ndw;                  // survivor dwords per stored row
     int row_stages;           // stages per stored row
@@ -330,6 +369,7 @@ int64_t waves_per_launch(const pbvd_plan *p, int64_t sp_wave_dwords) {
 int call_lb(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
     const int req = requested_lb(p->code);
     if (req >= 0) return req;
+    if (p->code_idx < 0 || pb_count <= p->wave_max_pbs) return kWaveLb;
     const int top = max_lb(p->code);
     if (top == 0) return 0;
     if (p->code.K <= 7 && call_geometry(p->code, n_bits, pb_first, pb_count, 0).n_waves >= 4096) return 0;
@@ -349,6 +389,79 @@ pbvd_status validate_call(const pbvd_plan *p, const void *d_syms, int64_t n_bits
     return PBVD_OK;
 }
 
+// The state-parallel kernel for one call: one wave per PB, in launches of
+// as many PBs as the survivor workspace holds.
+pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
+                            int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
+                            hipStream_t stream, CallGeometry *geo_out, bool single_launch) {
+    const pbvd_code &c = p->code;
+    const int64_t D = c.D;
+    const int64_t T = n_bits + (c.terminated ? c.K - 1 : 0);
+    if (geo_out) {
+        *geo_out = CallGeometry{};
+        geo_out->T = T;
+        geo_out->pb_first = pb_first;
+        geo_out->pb_end = pb_first + pb_count;
+        geo_out->n_waves = pb_count;
+    }
+    if (pb_count == 0) return PBVD_OK;
+    const int64_t slot = wave_slot_dwords(c);
+    const int64_t per_launch = std::max<int64_t>(1, p->budget_bytes / (slot * 4));
+    if (single_launch && pb_count > per_launch)
+        return fail(PBVD_EINVAL, "%lld PBs do not fit one launch (limit %lld)", (long long)pb_count,
+                    (long long)per_launch);
+    if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
+    const int64_t launch_pbs = std::min(pb_count, per_launch);
+    pbvd_status st = ensure_buffer(&ws.sp, &ws.sp_bytes, (size_t)(launch_pbs * slot * 4), "survivors");
+    if (st != PBVD_OK) return st;
+    const int64_t end_bit = std::min(n_bits, (pb_first + pb_count) * D);
+    const int64_t out_bits = end_bit - pb_first * D;
+    const int64_t out_bytes = ceil_div(out_bits, 8);
+    const bool direct = (D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
+    if (!direct) {
+        const int64_t nwords = ceil_div(out_bits, 32) + 2;
+        st = ensure_buffer(&ws.words, &ws.words_bytes, (size_t)nwords * 4, "output staging");
+        if (st != PBVD_OK) return st;
+        hipError_t e = pbvd::fill_u32(ws.words, nwords, 0u, stream);
+        if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
+    }
+    pbvd::WaveLaunchRequest req{};
+    pbvd::wave::Args &a = req.args;
+    a.syms = (const uint8_t *)d_syms;
+    a.in_end = a.syms + T * c.R;
+    a.out = d_out;
+    a.out_words = direct ? nullptr : ws.words;
+    a.out_bytes = out_bytes;
+    a.final_pm = d_final_pm;
+    a.sp = ws.sp;
+    a.sp_wave_dwords = slot;
+    a.n = n_bits;
+    a.T = T;
+    a.pb_first = pb_first;
+    a.D = c.D;
+    a.L = c.L;
+    a.terminated = c.terminated;
+    a.out_mode = direct ? pbvd::kOutDirect : pbvd::kOutAtomic;
+    a.descs = nullptr;
+    for (int r = 0; r < 4; ++r) a.gen[r] = r < c.R ? c.gen[r] : 0u;
+    req.R = c.R;
+    req.input_kind = c.input_kind;
+    req.stream = stream;
+    const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
+    for (int64_t w0 = 0; w0 < pb_count; w0 += launch_pbs) {
+        a.wave_begin = w0;
+        a.n_waves = std::min(launch_pbs, pb_count - w0);
+        req.grid = (unsigned)ceil_div(a.n_waves, waves_per_block);
+        hipError_t e = launch_wave(c.K, req);
+        if (e != hipSuccess) return fail_hip(e, "wave decode kernel launch");
+    }
+    if (!direct) {
+        hipError_t e = pbvd::words_to_bytes(ws.words, d_out, out_bytes, stream);
+        if (e != hipSuccess) return fail_hip(e, "output copy launch");
+    }
+    return PBVD_OK;
+}
+
 // Runs the decode kernels of one call; fills *geo with the decomposition.
 pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
                        int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
@@ -356,6 +469,11 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
                        int *lb_out = nullptr) {
     const pbvd_code &c = p->code;
     const int lb = call_lb(p, n_bits, pb_first, pb_count);
+    if (lb == kWaveLb) {
+        if (lb_out) *lb_out = lb;
+        return run_decode_wave(p, ws, d_syms, n_bits, pb_first, pb_count, d_out, d_final_pm, stream,
+                               geo_out, single_launch);
+    }
     const int64_t sp_wave_dwords = slot_dwords(c, lb);
     const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count, lb, d_final_pm ? 0 : p->n_simd);
     if (geo_out) *geo_out = g;
@@ -449,6 +567,10 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
         cus = 256;
     (void)hipGetLastError();
     p->n_simd = 4 * (int64_t)cus;
+    // the wave kernel runs a PB 64 lanes wide; the register kernel is faster
+    // once a call has enough PBs to fill the device with lanes
+    p->wave_max_pbs = c.K <= 7 ? 16384 : 8192;
+    if (const char *env = getenv("PBVD_WAVE_MAX_PBS")) p->wave_max_pbs = atoll(env);
     // PBVD_FOLD_SIMDS overrides the SIMD count of the edge-folding rule
     // (1: fold whenever it saves a wave, 0: never fold)
     if (const char *env = getenv("PBVD_FOLD_SIMDS")) p->n_simd = atoll(env) < 0 ? 0 : atoll(env);
@@ -524,7 +646,8 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     if (st != PBVD_OK || pb_count == 0) return st;
     pbvd::SurvivorView v{};
     v.sp = p->ws.sp;
-    v.sp_wave_dwords = slot_dwords(p->code, lb);
+    v.wave = lb == kWaveLb ? 1 : 0;
+    v.sp_wave_dwords = lb == kWaveLb ? wave_slot_dwords(p->code) : slot_dwords(p->code, lb);
     v.lb = lb;
     v.T = g.T;
     v.pb_first = pb_first;

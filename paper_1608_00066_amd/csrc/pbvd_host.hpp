@@ -35,14 +35,26 @@ struct DeviceGuard {
 // Grows a device buffer to at least `need` bytes (contents are not kept).
 pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char *what);
 
-// Validates a code/block parameter set; *idx_out receives its registry index.
+// log2 of the lanes per PB of the state-parallel kernel (a whole wave).
+constexpr int kWaveLb = 6;
+
+// Validates a code/block parameter set; *idx_out receives its registry index
+// (-1: no register kernel; the wave mapping decodes it).
 pbvd_status check_code(const pbvd_code &c, int *idx_out);
+
+// Survivor dwords of one wave slot of the state-parallel kernel (one PB of
+// at most D + 2L forward stages).
+int64_t wave_slot_dwords(const pbvd_code &c);
+
+// Launches the state-parallel kernel of constraint length req.K.
+hipError_t launch_wave(int K, const pbvd::WaveLaunchRequest &req);
 
 // Survivor dwords of one wave slot of a code (all D + 2L forward rows) with
 // 2^lb lanes per PB.
 int64_t slot_dwords(const pbvd_code &c, int lb);
 
-// log2 of the lanes per PB a code asks for (-1: the library chooses).
+// log2 of the lanes per PB a code asks for (kWaveLb for the wave mapping,
+// -1: the library chooses).
 int requested_lb(const pbvd_code &c);
 // The largest lane group a code supports.
 int max_lb(const pbvd_code &c);
@@ -66,9 +78,14 @@ struct CodeSet {
 
 // Validates n codes for batched use (D % 8 == 0) into *out.  Codes that let
 // the library choose their lanes per PB get auto_lb (clipped to what the
-// code supports; -1: the largest it supports).
+// code supports; -1: the largest it supports); codes without a register
+// kernel, or that ask for the wave mapping, get kWaveLb.
 pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int auto_lb = 0);
 
+// The work of one code: tiles of the register kernel (waves of 64 >> lb
+// PBs; tile_begin indexes the heads, 64 lane descriptors per tile), or, with
+// lb == kWaveLb, PBs of the state-parallel kernel (one wave each;
+// tile_begin indexes the PB descriptors).
 struct TileGroup {
     int64_t tile_begin = 0, n_tiles = 0;
     int64_t sp_wave_dwords = 0;
@@ -77,8 +94,9 @@ struct TileGroup {
 
 // Tiles (waves of 64 PBs) of a set of frames, grouped by code.
 struct WorkList {
-    std::vector<pbvd::LaneDesc> lanes;   // 64 per tile
-    std::vector<pbvd::TileHead> heads;   // one per tile
+    std::vector<pbvd::LaneDesc> lanes;   // 64 per tile (register kernel)
+    std::vector<pbvd::TileHead> heads;   // one per tile (register kernel)
+    std::vector<pbvd::LaneDesc> descs;   // one per PB (state-parallel kernel)
     TileGroup groups[kMaxCodes];
     int64_t n_blocks = 0, n_stages = 0;
 };
@@ -92,7 +110,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
 // the survivor area `sp` one launch after another.
 pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const uint8_t *d_syms,
                          int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
-                         const pbvd::TileHead *d_heads, uint32_t *sp, int64_t per_launch,
-                         hipStream_t stream);
+                         const pbvd::TileHead *d_heads, const pbvd::LaneDesc *d_descs, uint32_t *sp,
+                         int64_t per_launch, hipStream_t stream);
 
 }  // namespace pbvd_host

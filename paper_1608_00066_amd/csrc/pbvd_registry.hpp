@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "pbvd_kernel.hpp"
+#include "pbvd_wave.hpp"
 
 // X(index, K, R, g0, g1, g2, g3): generators in octal, gen[r] bit k = g_k.
 // The first four are the codes of the benchmark workloads; the others are
@@ -71,6 +72,18 @@ template <int IDX>
 hipError_t launch_code(const LaunchRequest &req);
 template <int IDX>
 hipError_t launch_tiles(const TileLaunchRequest &req);
+
+// State-parallel kernel (one wave per PB, run-time generators).
+struct WaveLaunchRequest {
+    wave::Args args;
+    int R;
+    int input_kind;
+    unsigned grid;       // workgroups of kBlockThreads (4 PBs each)
+    hipStream_t stream;
+};
+// Implemented by the translation unit compiled for constraint length K.
+template <int K>
+hipError_t launch_wave(const WaveLaunchRequest &req);
 
 // Survivor layout of a code: dwords per stored row and stages per row.
 __host__ __device__ constexpr int survivor_row_dwords(int K) { return (1 << (K - 2)) >= 16 ? (1 << (K - 2)) / 16 : 1; }

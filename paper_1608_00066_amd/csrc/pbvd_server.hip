@@ -91,26 +91,42 @@ struct Footprint {
         pbs[r.code] += r.n_pbs - r.n_argmin_pbs;
         argmin[r.code] += r.n_argmin_pbs;
     }
-    // lb[] of the code set: 64 >> lb PBs per tile
+    // lb[] of the code set: 64 >> lb PBs per tile; the state-parallel
+    // kernel (kWaveLb) takes one PB per wave and one descriptor per PB
     int64_t tiles(int ci, const CodeSet &cs) const {
+        if (cs.lb[ci] == kWaveLb) return pbs[ci] + argmin[ci];
         return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + argmin[ci];
     }
     int64_t lanes_bytes(const CodeSet &cs) const {
         int64_t t = 0;
-        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci, cs);
+        for (int ci = 0; ci < cs.n; ++ci)
+            if (cs.lb[ci] != kWaveLb) t += tiles(ci, cs);
         return align_up(t * pbvd::kWave * (int64_t)sizeof(pbvd::LaneDesc));
     }
     int64_t heads_bytes(const CodeSet &cs) const {
         int64_t t = 0;
-        for (int ci = 0; ci < cs.n; ++ci) t += tiles(ci, cs);
+        for (int ci = 0; ci < cs.n; ++ci)
+            if (cs.lb[ci] != kWaveLb) t += tiles(ci, cs);
         return align_up(t * (int64_t)sizeof(pbvd::TileHead));
+    }
+    int64_t descs_bytes(const CodeSet &cs) const {
+        int64_t t = 0;
+        for (int ci = 0; ci < cs.n; ++ci)
+            if (cs.lb[ci] == kWaveLb) t += tiles(ci, cs);
+        return align_up(t * (int64_t)sizeof(pbvd::LaneDesc));
     }
     int64_t sp_bytes(const CodeSet &cs) const {
         int64_t b = 0;
-        for (int ci = 0; ci < cs.n; ++ci) b += align_up(tiles(ci, cs) * slot_dwords(cs.codes[ci], cs.lb[ci]) * 4);
+        for (int ci = 0; ci < cs.n; ++ci) {
+            const int64_t per = cs.lb[ci] == kWaveLb ? wave_slot_dwords(cs.codes[ci])
+                                                     : slot_dwords(cs.codes[ci], cs.lb[ci]);
+            b += align_up(tiles(ci, cs) * per * 4);
+        }
         return b;
     }
-    int64_t in_bytes(const CodeSet &cs) const { return align_up(sym) + lanes_bytes(cs) + heads_bytes(cs); }
+    int64_t in_bytes(const CodeSet &cs) const {
+        return align_up(sym) + lanes_bytes(cs) + heads_bytes(cs) + descs_bytes(cs);
+    }
     int64_t device_bytes(const CodeSet &cs) const { return in_bytes(cs) + align_up(out) + sp_bytes(cs); }
 };
 
@@ -186,11 +202,12 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
     WorkList wl;
     pbvd_status st = build_work_list(cs, frames.data(), n, sym_total, out_total, &wl);
     if (st != PBVD_OK) return st;
-    // layout (device and pinned-in share the first three parts):
-    // [symbols | lanes | heads | outputs | survivors of code 0 | code 1 ...]
+    // layout (device and pinned-in share the first four parts):
+    // [symbols | lanes | heads | descs | outputs | survivors of code 0 | code 1 ...]
     const int64_t lanes_off = align_up(sym_total);
     const int64_t heads_off = lanes_off + align_up((int64_t)(wl.lanes.size() * sizeof(pbvd::LaneDesc)));
-    const int64_t in_total = heads_off + align_up((int64_t)(wl.heads.size() * sizeof(pbvd::TileHead)));
+    const int64_t descs_off = heads_off + align_up((int64_t)(wl.heads.size() * sizeof(pbvd::TileHead)));
+    const int64_t in_total = descs_off + align_up((int64_t)(wl.descs.size() * sizeof(pbvd::LaneDesc)));
     const int64_t out_dev = in_total;
     int64_t sp_off[kMaxCodes], end = out_dev + align_up(out_total);
     for (int ci = 0; ci < cs.n; ++ci) {
@@ -202,6 +219,7 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
                     (long long)sv->slot_bytes);
     memcpy(sl.pin_in + lanes_off, wl.lanes.data(), wl.lanes.size() * sizeof(pbvd::LaneDesc));
     memcpy(sl.pin_in + heads_off, wl.heads.data(), wl.heads.size() * sizeof(pbvd::TileHead));
+    memcpy(sl.pin_in + descs_off, wl.descs.data(), wl.descs.size() * sizeof(pbvd::LaneDesc));
 
     hipError_t e = hipMemcpyAsync(sl.dev, sl.pin_in, (size_t)in_total, hipMemcpyHostToDevice, sl.stream);
     if (e != hipSuccess) return fail_hip(e, "request upload");
@@ -211,6 +229,7 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
     const uint8_t *d_syms = sl.dev;
     const pbvd::LaneDesc *d_lanes = reinterpret_cast<const pbvd::LaneDesc *>(sl.dev + lanes_off);
     const pbvd::TileHead *d_heads = reinterpret_cast<const pbvd::TileHead *>(sl.dev + heads_off);
+    const pbvd::LaneDesc *d_descs = reinterpret_cast<const pbvd::LaneDesc *>(sl.dev + descs_off);
     uint8_t *d_out = sl.dev + out_dev;
     // the codes run one after another on the slot's stream, cheapest first
     // (2^K R), each followed by its read-back and completion event: a code's
@@ -223,7 +242,7 @@ pbvd_status launch_slot(pbvd_server *sv, Slot &sl) {
     });
     for (int k = 0; k < n_active; ++k) {
         const int ci = active[k];
-        st = launch_group(cs, ci, wl.groups[ci], d_syms, sym_total, d_out, d_lanes, d_heads,
+        st = launch_group(cs, ci, wl.groups[ci], d_syms, sym_total, d_out, d_lanes, d_heads, d_descs,
                           reinterpret_cast<uint32_t *>(sl.dev + sp_off[ci]), wl.groups[ci].n_tiles, sl.stream);
         if (st != PBVD_OK) return st;
         e = hipMemcpyAsync(sl.pin_out + out_lo[ci], d_out + out_lo[ci], (size_t)(out_hi[ci] - out_lo[ci]),

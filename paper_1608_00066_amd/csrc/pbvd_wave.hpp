@@ -1,0 +1,506 @@
+// State-parallel decoder kernel: one wave decodes one parallel block (PB) of
+// the parallel block-based Viterbi decoder (arXiv 1608.00066, Sec. III-A),
+// one lane per trellis state (Sec. IV-A spreads a PB over threads in the
+// same spirit: every thread updates a part of the states of each stage).
+//
+// Unlike the register kernel of pbvd_kernel.hpp (one lane per PB, the code a
+// compile-time parameter) this kernel takes the generators as run-time
+// arguments, so it decodes any rate-1/R code with 3 <= K <= 9, R <= 4, and a
+// PB's D + 2L stages run 64 lanes wide: a short stream or a single frame
+// finishes in a few microseconds instead of the hundreds a lane needs.
+//
+// Position map.  State d of stage t lives at position u = rotl_V^(t mod V)(d)
+// (V = K-1 bits).  Then the butterfly of Sec. III-B at stage t pairs the
+// positions that differ in bit ph = t mod V: the even one holds the upper
+// predecessor S_2j, the odd one S_2j+1, and the new metrics of S_j (input 0)
+// and S_j+2^(V-1) (input 1) go back to the even and the odd position.
+// Position u is lane u mod 64, register slot u / 64 (K = 8: 2 slots, K = 9:
+// 4).  For K < 7 the lanes above 2^V repeat the low ones.
+//
+// Exchanges.  At phase ph every position needs the metric of the pair's
+// even and odd position: lane bits 0 and 1 with DPP quad permutes, bits 2
+// and 3 with DPP row shifts restricted to the banks that read across, bit 4
+// and 5 with the gfx950 permlane16/permlane32 swaps (one instruction gives
+// both halves), slot bits inside the lane.
+//
+// Branch metrics.  A branch's code word is c = (c^(1)..c^(R)) of Eq. 2; its
+// metric is sum over r of c_r q_r (the Sec. II distance minus a constant
+// shared by all branches of the stage, which changes no decision).  Each lane
+// keeps, per phase and slot, the code-word bits of its two branches as byte
+// masks and forms each metric with one v_dot4_i32_i8 of the stage's R
+// symbols (packed in one dword) and the mask.
+//
+// Survivors.  dec = 1 when the lower branch (from S_2j+1) is strictly
+// cheaper, as Eq. 1 with ties to the upper branch; a lane shifts its
+// decision into one dword per slot every stage (v_alignbit), and every W
+// stages (the trip, W = V * floor(32 / V), so a trip starts at phase 0) the
+// dwords go to HBM: [trip][slot][lane], bit W-1-k for the k-th stage of the
+// trip.  The decision stored at position u in stage t belongs to the state
+// rotr_V^((t+1) mod V)(u) after the stage.
+//
+// Traceback (Alg. 1, Kernel 2).  Wave-uniform, on the scalar unit: the
+// traced state is kept as a position P; at stage t its input bit is bit
+// t mod V of P, and the predecessor's position is P with that bit replaced
+// by the stored decision of lane P mod 64 (v_readlane).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "pbvd_kernel.hpp"
+
+namespace pbvd {
+namespace wave {
+
+// Stages per survivor dword: a whole number of phase cycles.
+__host__ __device__ constexpr int trip_stages(int V) { return V * (32 / V); }
+// Register slots per lane (2^V states over 64 lanes).
+__host__ __device__ constexpr int slots(int V) { return V > 6 ? 1 << (V - 6) : 1; }
+// Survivor dwords of one PB of len forward stages.
+__host__ __device__ constexpr int64_t pb_dwords(int V, int64_t len) {
+    return (len + trip_stages(V) - 1) / trip_stages(V) * slots(V) * kWave;
+}
+
+struct Args {
+    const uint8_t *syms;     // symbols; stream mode: stage 0 of the stream
+    const uint8_t *in_end;   // end of the readable symbol bytes
+    uint8_t *out;            // packed decoded bits
+    uint32_t *out_words;     // zeroed word staging (atomic output) or null
+    int64_t out_bytes;       // bytes of `out` (direct output bound)
+    int32_t *final_pm;       // [PB][2^V] normalized final metrics or null
+    uint32_t *sp;            // survivor scratch, sp_wave_dwords per wave
+    int64_t sp_wave_dwords;
+    // stream mode (descs == null): PBs [pb_first + wave_begin, + n_waves)
+    int64_t n, T, pb_first;
+    int32_t D, L, terminated;
+    int32_t out_mode;        // kOutDirect / kOutAtomic / kOutBytes
+    // tile mode: one descriptor per PB (lane descriptor of the batch work list)
+    const LaneDesc *descs;
+    int64_t wave_begin;      // first PB of this launch (relative to pb_first / descs)
+    int64_t n_waves;         // PBs of this launch
+    uint32_t gen[4];         // generators (gen[r] bit k = g_k of Eq. 2), 0 past R
+};
+
+// Even and odd position's value of the pair whose bit is lane bit B.
+template <int B>
+__device__ __forceinline__ void pair_values(int v, int &e, int &o) {
+    if constexpr (B == 0) {
+        e = __builtin_amdgcn_mov_dpp(v, quad_sel(0, 0, 2, 2), 0xf, 0xf, false);
+        o = __builtin_amdgcn_mov_dpp(v, quad_sel(1, 1, 3, 3), 0xf, 0xf, false);
+    } else if constexpr (B == 1) {
+        e = __builtin_amdgcn_mov_dpp(v, quad_sel(0, 1, 0, 1), 0xf, 0xf, false);
+        o = __builtin_amdgcn_mov_dpp(v, quad_sel(2, 3, 2, 3), 0xf, 0xf, false);
+    } else if constexpr (B == 2) {
+        // banks (groups of 4 lanes) 1 and 3 read 4 lanes down, 0 and 2 up
+        e = __builtin_amdgcn_update_dpp(v, v, 0x114, 0xf, 0xa, false);
+        o = __builtin_amdgcn_update_dpp(v, v, 0x104, 0xf, 0x5, false);
+    } else if constexpr (B == 3) {
+        e = __builtin_amdgcn_update_dpp(v, v, 0x118, 0xf, 0xc, false);
+        o = __builtin_amdgcn_update_dpp(v, v, 0x108, 0xf, 0x3, false);
+    } else if constexpr (B == 4) {
+        // rows 1, 3 of the first operand swap with rows 0, 2 of the second:
+        // the first result holds rows (0, 0, 2, 2), the second (1, 1, 3, 3)
+        const auto r = __builtin_amdgcn_permlane16_swap((unsigned)v, (unsigned)v, false, false);
+        e = (int)r[0];
+        o = (int)r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap((unsigned)v, (unsigned)v, false, false);
+        e = (int)r[0];
+        o = (int)r[1];
+    }
+}
+
+// acc + (dot product of the symbol dword of lane LANE of the row and mask):
+// v_dot4c_i32_i8 with the symbols broadcast by DPP row_newbcast (written out:
+// the compiler does not fold the broadcast into the dot product).
+template <int LANE>
+__device__ __forceinline__ int dot_bcast(int acc, uint32_t qv, uint32_t mask) {
+    asm("v_dot4c_i32_i8_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+        : "+v"(acc)
+        : "v"(qv), "v"(mask), "n"(LANE));
+    return acc;
+}
+
+// acc << 1 | (diff's sign bit)
+__device__ __forceinline__ uint32_t push_sign(uint32_t acc, int diff) {
+    return __builtin_amdgcn_alignbit(acc, (uint32_t)diff, 31);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int m = 1; m < kWave; m <<= 1) v = min(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+__device__ __forceinline__ int parity32(uint32_t x) { return __builtin_popcount(x) & 1; }
+
+// A 64-bit value every lane holds alike, made provably wave-uniform.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+template <int V>
+__device__ __forceinline__ uint32_t rotr_rt32(uint32_t u, int s) {
+    s %= V;
+    return s == 0 ? u : (((u >> s) | (u << (V - s))) & ((1u << V) - 1u));
+}
+
+// The PB a wave decodes.
+struct Job {
+    const uint8_t *in;   // symbols of the first forward stage
+    int len;             // forward stages
+    int store0;          // first traced (decoded) stage
+    int dec_end;         // end of the decoded range (stage index)
+    bool known;          // starts from encoder state 0
+    bool argmin;         // traceback from the least-metric state
+    int64_t out_bit0;    // output bit of the first decoded stage
+    int32_t *pm_out;     // final metrics or null
+};
+
+template <int V, int R, int KIND>
+__device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t *sp_wave) {
+    constexpr int N = 1 << V;
+    constexpr int SL = slots(V);
+    constexpr int NL = N < kWave ? N : kWave;   // distinct positions per slot
+    constexpr int LB = V < 6 ? V : 6;            // lane bits of a position
+    constexpr int W = trip_stages(V);
+    constexpr int G = (W + 15) / 16;             // symbol dwords per lane and trip
+
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const int len = j.len;
+    // Trips are aligned to the end of the forward range: trip i holds
+    // stages [i*W - off, (i+1)*W - off), so the first trip starts off
+    // stages in and the last one ends at stage len, at phase 0.
+    const int n_trips = (len + W - 1) / W;
+    const int off = n_trips * W - len;
+
+    // ---- per-lane code-word masks of the two branches into each position,
+    //      per phase and slot (Eq. 2 with the run-time generators) ----
+    uint32_t mup[V][SL], mlo[V][SL];
+#pragma unroll
+    for (int ph = 0; ph < V; ++ph) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const uint32_t u = (uint32_t)(s * kWave + (lane & (NL - 1)));
+            const uint32_t even = u & ~(1u << ph);
+            const uint32_t se = rotr_rt32<V>(even, ph);   // the upper predecessor S_2j
+            const uint32_t x = (u >> ph) & 1u;             // input bit of the branch
+            const uint32_t reg = (x << V) | se;
+            uint32_t mu = 0, ml = 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                mu |= (uint32_t)parity32(a.gen[r] & reg) << (8 * r);
+                ml |= (uint32_t)parity32(a.gen[r] & (reg | 1u)) << (8 * r);
+            }
+            mup[ph][s] = mu;
+            mlo[ph][s] = ml;
+        }
+    }
+
+    // ---- initial metrics: with a known start, state 0 (position 0 at any
+    //      phase) at 0 and the others at 8192; otherwise all 0 ----
+    int pm[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int u = s * kWave + (lane & (NL - 1));
+        pm[s] = (j.known && u != 0) ? 8192 : 0;
+    }
+
+    uint32_t *const sp_lane = sp_wave + lane;  // [trip][slot][lane]
+
+    // Symbols: the R symbols of stage t are packed in one dword (bytes
+    // 0..R-1; the bytes above belong to the next stage and meet zero mask
+    // bytes).  Lane l holds those of the trip's stage g*16 + (l mod 16) in
+    // qv[g] (every row of 16 lanes the same), and each stage broadcasts its
+    // dword from lane k mod 16 of every row into the dot product (DPP
+    // row_newbcast).  A trip's symbols are loaded a trip ahead.
+    const uint8_t *const in = j.in;
+    const int sl = lane & 15;
+    auto load_q = [&](uint32_t (&lo)[G], uint32_t (&hi)[G], uint32_t (&mis)[G], int tt0) PBVD_INLINE_LAMBDA {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            int t = tt0 + g * 16 + sl;
+            t = t < 0 ? 0 : t;  // stages before the first are never used
+            const uint8_t *p = in + (int64_t)t * R;
+            mis[g] = (uint32_t)((uintptr_t)p & 3u);
+            const uint8_t *pa = p - mis[g];
+            if (pa + 8 <= a.in_end) {
+                const uint32_t *w = reinterpret_cast<const uint32_t *>(pa);
+                lo[g] = __builtin_nontemporal_load(w);
+                hi[g] = __builtin_nontemporal_load(w + 1);
+            } else {
+                // the end of the input (bytes past it read as 0)
+                uint32_t v0 = 0u, v1 = 0u;
+#pragma unroll
+                for (int bb = 0; bb < 4; ++bb) {
+                    if (pa + bb < a.in_end) v0 |= (uint32_t)pa[bb] << (8 * bb);
+                    if (pa + 4 + bb < a.in_end) v1 |= (uint32_t)pa[4 + bb] << (8 * bb);
+                }
+                lo[g] = v0;
+                hi[g] = v1;
+            }
+        }
+    };
+    auto make_q = [&](const uint32_t (&lo)[G], const uint32_t (&hi)[G], const uint32_t (&mis)[G],
+                      uint32_t (&qv)[G]) PBVD_INLINE_LAMBDA {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            uint32_t q = __builtin_amdgcn_alignbyte(hi[g], lo[g], mis[g]);
+            if constexpr (KIND == kHardU8) q = 0x01010101u + (q & 0x01010101u) * 0xfeu;  // bit -> +1 / -1
+            qv[g] = q;
+        }
+        // two wait states between these writes and the DPP reads of qv
+        if constexpr (G == 1) asm volatile("s_nop 1" : "+v"(qv[0]));
+        else asm volatile("s_nop 1" : "+v"(qv[0]), "+v"(qv[1]));
+    };
+
+    // one trellis stage, the k-th of its trip (phase k mod V); each
+    // candidate is its predecessor's metric plus the branch metric, the dot
+    // product accumulating onto the exchanged metric
+    auto stage = [&](auto kc, const uint32_t (&qv)[G], uint32_t (&acc)[SL]) PBVD_INLINE_LAMBDA {
+        constexpr int k = decltype(kc)::value;
+        constexpr int PH = k % V;
+        const uint32_t q = qv[k / 16];
+        if constexpr (PH < LB) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                int e, o;
+                pair_values<PH>(pm[s], e, o);
+                const int up = dot_bcast<k % 16>(e, q, mup[PH][s]);
+                const int lo = dot_bcast<k % 16>(o, q, mlo[PH][s]);
+                acc[s] = push_sign(acc[s], lo - up);
+                pm[s] = min(up, lo);
+            }
+        } else {
+            constexpr int M = 1 << (PH - 6);  // slot bit
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                if (s & M) continue;
+                const int e = pm[s], o = pm[s | M];
+                const int up0 = dot_bcast<k % 16>(e, q, mup[PH][s]);
+                const int lo0 = dot_bcast<k % 16>(o, q, mlo[PH][s]);
+                const int up1 = dot_bcast<k % 16>(e, q, mup[PH][s | M]);
+                const int lo1 = dot_bcast<k % 16>(o, q, mlo[PH][s | M]);
+                acc[s] = push_sign(acc[s], lo0 - up0);
+                acc[s | M] = push_sign(acc[s | M], lo1 - up1);
+                pm[s] = min(up0, lo0);
+                pm[s | M] = min(up1, lo1);
+            }
+        }
+    };
+
+    // ---- forward procedure (Eq. 1) ----
+    uint32_t nlo[G], nhi[G], nmis[G];
+    load_q(nlo, nhi, nmis, -off);
+    for (int trip = 0; trip < n_trips; ++trip) {
+        const int tt0 = trip * W - off;  // stage of the trip's step 0
+        uint32_t qv[G];
+        make_q(nlo, nhi, nmis, qv);
+        if (trip + 1 < n_trips) load_q(nlo, nhi, nmis, tt0 + W);  // a trip ahead
+        uint32_t acc[SL];
+#pragma unroll
+        for (int s = 0; s < SL; ++s) acc[s] = 0;
+        if (trip > 0 || off == 0) {
+            static_for<0, W>([&](auto kc) PBVD_INLINE_LAMBDA {
+                stage(kc, qv, acc);
+                return true;
+            });
+        } else {
+            // the first trip starts at step off (its lower bits stay 0)
+            static_for<0, W>([&](auto kc) PBVD_INLINE_LAMBDA {
+                if (decltype(kc)::value >= off) stage(kc, qv, acc);
+                return true;
+            });
+        }
+        // step k of the trip at bit W-1-k
+#pragma unroll
+        for (int s = 0; s < SL; ++s) __builtin_nontemporal_store(acc[s], sp_lane + (trip * SL + s) * kWave);
+        // exact renormalization: every metric minus one shared value
+        const int ref = __builtin_amdgcn_readfirstlane(pm[0]);
+#pragma unroll
+        for (int s = 0; s < SL; ++s) pm[s] -= ref;
+    }
+
+    // ---- final metrics and traceback start (Sec. III-A; Sec. II at the end
+    //      of an unterminated stream).  The forward range ends at phase 0:
+    //      position u holds state u. ----
+    uint32_t P = 0;
+    if (j.argmin || j.pm_out) {
+        int m = pm[0];
+#pragma unroll
+        for (int s = 1; s < SL; ++s) m = min(m, pm[s]);
+        m = wave_min(m);
+        if (j.argmin) {
+            int best = N;
+#pragma unroll
+            for (int s = 0; s < SL; ++s) {
+                const int u = s * kWave + (lane & (NL - 1));
+                if (pm[s] == m && u < best) best = u;
+            }
+            P = (uint32_t)__builtin_amdgcn_readfirstlane(wave_min(best));
+        }
+        if (j.pm_out && lane < NL) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s) j.pm_out[s * kWave + lane] = pm[s] - m;
+        }
+    }
+
+    // ---- traceback (Alg. 1, Kernel 2) ----
+    // Every step of a trip is traced (the last trip is full; steps below the
+    // decoded range at the bottom are harmless); the input bits of a trip
+    // collect in `word` (bit i = the trip's i-th stage) and the decoded ones
+    // are merged into the output word under assembly after the trip.
+    const int store0 = j.store0, dec_end = j.dec_end;
+    const int n_dec = dec_end - store0;
+    const int trip_bot = (store0 + off) / W;
+    uint32_t word = 0;
+    int cm = (n_dec - 1) >> 5;  // output word under assembly (relative to the PB)
+    uint32_t cw = 0;
+
+    auto flush = [&]() PBVD_INLINE_LAMBDA {
+        if (lane != 0) return;
+        const int rel = cm * 32;
+        const int m = n_dec - rel < 32 ? n_dec - rel : 32;
+        const int64_t bitpos = j.out_bit0 + rel;
+        if (a.out_mode == kOutDirect) {
+            const int64_t byte = bitpos >> 3;
+            if (m == 32 && byte + 4 <= a.out_bytes) {
+                *reinterpret_cast<uint32_t *>(a.out + byte) = cw;
+            } else {
+                for (int bb = 0; bb < ((m + 7) >> 3); ++bb)
+                    if (byte + bb < a.out_bytes) a.out[byte + bb] = (uint8_t)(cw >> (8 * bb));
+            }
+        } else if (a.out_mode == kOutAtomic) {
+            const uint32_t shf = (uint32_t)(bitpos & 31);
+            uint32_t *wp = a.out_words + (bitpos >> 5);
+            atomicOr(wp, cw << shf);
+            if (shf && (cw >> (32 - shf))) atomicOr(wp + 1, cw >> (32 - shf));
+        } else {
+            uint8_t *ob = a.out + (bitpos >> 3);
+            for (int bb = 0; bb < ((m + 7) >> 3); ++bb) ob[bb] = (uint8_t)(cw >> (8 * bb));
+        }
+    };
+
+    // survivor dwords of a trip, loaded a ring of trips ahead
+    constexpr int kRing = 3;
+    uint32_t ring[kRing][SL];
+    auto load_trip = [&](uint32_t (&dst)[SL], int trip) PBVD_INLINE_LAMBDA {
+        trip = trip < trip_bot ? trip_bot : trip;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) dst[s] = __builtin_nontemporal_load(sp_lane + (trip * SL + s) * kWave);
+    };
+    auto run_trip = [&](const uint32_t (&dw)[SL], int trip) PBVD_INLINE_LAMBDA {
+        static_for<0, W>([&](auto ic) PBVD_INLINE_LAMBDA {
+            constexpr int k = W - 1 - decltype(ic)::value;
+            constexpr int ph = k % V;
+            word = (word << 1) | ((P >> ph) & 1u);
+            uint32_t w;
+            if constexpr (SL == 1) {
+                w = (uint32_t)__builtin_amdgcn_readlane((int)dw[0], (int)(P & 63u));
+            } else {
+                const int l = (int)(P & 63u);
+                const uint32_t slot = P >> 6;
+                w = 0;
+#pragma unroll
+                for (int s = 0; s < SL; ++s) {
+                    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)dw[s], l);
+                    w = slot == (uint32_t)s ? v : w;
+                }
+            }
+            const uint32_t d = (w >> (W - 1 - k)) & 1u;
+            P = (P & ~(1u << ph)) | (d << ph);
+            return true;
+        });
+        // decoded stages of the trip: [lo, hi), at bits lo - tt0 .. of word
+        const int tt0 = trip * W - off;
+        const int lo = store0 > tt0 ? store0 : tt0;
+        const int hi = dec_end < tt0 + W ? dec_end : tt0 + W;
+        if (lo < hi) {
+            const int nb = hi - lo;
+            uint32_t bits = word >> (lo - tt0);
+            bits = nb >= 32 ? bits : bits & ((1u << nb) - 1u);
+            const int r = lo - store0;   // first decoded bit, relative
+            const int base = cm * 32;
+            if (r >= base) {
+                cw |= bits << (r - base);
+            } else {
+                // the chunk reaches into the word below: the current one is
+                // complete (r < base <= r + nb <= base + 32)
+                const int dn = base - r;  // 1..32 bits below the current word
+                if (dn < 32) cw |= bits >> dn;
+                flush();
+                --cm;
+                cw = dn < 32 ? bits << (32 - dn) : bits;
+            }
+        }
+    };
+
+    const int trip_top = n_trips - 1;
+    static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+        load_trip(ring[decltype(dc)::value], trip_top - decltype(dc)::value);
+        return true;
+    });
+    int trip = trip_top;
+    for (;;) {
+        const bool more = static_for<0, kRing>([&](auto dc) PBVD_INLINE_LAMBDA {
+            constexpr int d = decltype(dc)::value;
+            load_trip(ring[(d + kRing - 1) % kRing], trip - (kRing - 1));
+            run_trip(ring[d], trip);
+            if (trip <= trip_bot) return false;
+            --trip;
+            return true;
+        });
+        if (!more) break;
+    }
+    flush();  // word 0
+}
+
+// One wave per PB; 4 independent waves per 256-thread workgroup.
+// syms: the symbol buffer (the same pointer as a.syms), a separate parameter
+// so that its loads may use the scalar unit (nothing the kernel writes
+// aliases it).
+template <int V, int R, int KIND>
+__global__ void __launch_bounds__(256) decode_wave_kernel(const Args a, const uint8_t *__restrict__ syms) {
+    constexpr int N = 1 << V;
+    const int64_t wl = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                       __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wl >= a.n_waves) return;
+    const int64_t idx = a.wave_begin + wl;
+    Job j;
+    if (a.descs) {
+        const LaneDesc &d = a.descs[idx];
+        j.in = syms + uniform64(d.sym);
+        j.len = __builtin_amdgcn_readfirstlane(d.len);
+        j.store0 = __builtin_amdgcn_readfirstlane(d.store0);
+        j.dec_end = __builtin_amdgcn_readfirstlane(d.dec_end);
+        const int fl = __builtin_amdgcn_readfirstlane(d.flags);
+        j.known = (fl & kLaneKnown) != 0;
+        j.argmin = (fl & kLaneArgmin) != 0;
+        j.out_bit0 = uniform64(d.out_bit);
+        j.pm_out = nullptr;
+        if (!(fl & kLaneActive)) return;
+    } else {
+        const int64_t b = a.pb_first + idx;
+        const int64_t D = a.D, L = a.L;
+        const int64_t d0 = b * D;
+        const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
+        const int64_t f1 = d0 + D + L > a.T ? a.T : d0 + D + L;
+        const int64_t d1 = d0 + D > a.n ? a.n : d0 + D;
+        j.in = syms + f0 * R;
+        j.len = (int)(f1 - f0);
+        j.store0 = (int)(d0 - f0);
+        j.dec_end = (int)(d1 - f0);
+        j.known = f0 == 0;
+        j.argmin = f1 == a.T && !a.terminated;
+        j.out_bit0 = idx * D;
+        j.pm_out = a.final_pm ? a.final_pm + idx * N : nullptr;
+    }
+    decode_pb<V, R, KIND>(a, j, a.sp + wl * a.sp_wave_dwords);
+}
+
+}  // namespace wave
+}  // namespace pbvd

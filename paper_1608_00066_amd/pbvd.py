@@ -25,13 +25,16 @@ PBVD_EAGAIN = -5
 PBVD_SOFT_I8 = 0
 PBVD_HARD_U8 = 1
 PBVD_HOST_PINNED = 1
+PBVD_MAP_AUTO = 0
+PBVD_MAP_LANES = 1
+PBVD_MAP_WAVE = 2
 
 
 class pbvd_code(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("R", ctypes.c_int32), ("gen", ctypes.c_uint32 * 4),
                 ("D", ctypes.c_int32), ("L", ctypes.c_int32), ("terminated", ctypes.c_int32),
                 ("input_kind", ctypes.c_int32), ("pm_bits", ctypes.c_int32),
-                ("lanes_per_pb", ctypes.c_int32)]
+                ("lanes_per_pb", ctypes.c_int32), ("mapping", ctypes.c_int32)]
 
 
 class pbvd_frame(ctypes.Structure):
@@ -139,9 +142,10 @@ def _dev_ptr(t, what, min_bytes, dtypes):
 
 
 def pbvd_create(K: int, gens, D: int, L: int, terminated: bool = True,
-                input_kind: int = PBVD_SOFT_I8, pm_bits: int = 16, lanes_per_pb: int = 0) -> int:
+                input_kind: int = PBVD_SOFT_I8, pm_bits: int = 16, lanes_per_pb: int = 0,
+                mapping: int = PBVD_MAP_AUTO) -> int:
     """Returns an opaque plan handle (int)."""
-    c = _code_struct(K, gens, D, L, terminated, input_kind, pm_bits, lanes_per_pb)
+    c = _code_struct(K, gens, D, L, terminated, input_kind, pm_bits, lanes_per_pb, mapping)
     h = ctypes.c_void_p()
     _check(lib().pbvd_create(ctypes.byref(c), ctypes.byref(h)), "pbvd_create")
     return h.value
@@ -166,12 +170,15 @@ class Plan:
     """One decoder plan (code + block parameters + its device workspace)."""
 
     def __init__(self, K: int, gens, D: int, L: int, terminated: bool = True,
-                 input_kind: int = PBVD_SOFT_I8, pm_bits: int = 16, lanes_per_pb: int = 0):
+                 input_kind: int = PBVD_SOFT_I8, pm_bits: int = 16, lanes_per_pb: int = 0,
+                 mapping: int = PBVD_MAP_AUTO):
         self.K, self.gens, self.R = K, tuple(int(g) for g in gens), len(gens)
         self.D, self.L, self.terminated = D, L, bool(terminated)
         self.input_kind, self.pm_bits, self.lanes_per_pb = input_kind, pm_bits, lanes_per_pb
+        self.mapping = mapping
         self.N = 1 << (K - 1)
-        self.handle = pbvd_create(K, gens, D, L, terminated, input_kind, pm_bits, lanes_per_pb)
+        self.handle = pbvd_create(K, gens, D, L, terminated, input_kind, pm_bits, lanes_per_pb,
+                                  mapping)
 
     def close(self):
         if self.handle:
@@ -304,13 +311,14 @@ def unpack_bits(packed: np.ndarray, n_bits: int) -> np.ndarray:
 
 
 def _code_struct(K, gens, D, L, terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16,
-                 lanes_per_pb=0):
+                 lanes_per_pb=0, mapping=PBVD_MAP_AUTO):
     c = pbvd_code()
     c.K, c.R = K, len(gens)
     for i, g in enumerate(gens[:4]):
         c.gen[i] = int(g)
     c.D, c.L, c.terminated, c.input_kind, c.pm_bits = D, L, int(terminated), input_kind, pm_bits
     c.lanes_per_pb = lanes_per_pb
+    c.mapping = mapping
     return c
 
 
@@ -318,10 +326,11 @@ class Batch:
     """pbvd_batch_*: many frames, several codes, one launch per code.
 
     ``codes`` is a list of dicts with keys K, gens, D, L and optionally
-    terminated, input_kind, pm_bits, lanes_per_pb."""
+    terminated, input_kind, pm_bits, lanes_per_pb, mapping."""
 
     def __init__(self, codes):
-        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16, lanes_per_pb=0)
+        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16, lanes_per_pb=0,
+                        mapping=PBVD_MAP_AUTO)
         self.codes = [{**defaults, **c} for c in codes]
         arr = (pbvd_code * len(codes))(*[_code_struct(**c) for c in self.codes])
         h = ctypes.c_void_p()
@@ -385,7 +394,8 @@ class Server:
 
     def __init__(self, codes, device_bytes: int = 256 << 20, max_inflight: int = 4,
                  max_batch_frames: int = 1024, max_queued: int = 1 << 20):
-        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16, lanes_per_pb=0)
+        defaults = dict(terminated=True, input_kind=PBVD_SOFT_I8, pm_bits=16, lanes_per_pb=0,
+                        mapping=PBVD_MAP_AUTO)
         self.codes = [{**defaults, **c} for c in codes]
         arr = (pbvd_code * len(codes))(*[_code_struct(**c) for c in self.codes])
         cfg = pbvd_server_config(int(device_bytes), int(max_inflight), int(max_batch_frames),

@@ -50,8 +50,11 @@ def test_strerror(pbvd):
     (dict(gens=(0o171, 0o1133)), -1), (dict(gens=(0o71, 0o33)), -1), (dict(gens=(0o171, 0)), -1),
     (dict(D=0), -1), (dict(L=-1), -1), (dict(D=1 << 29, L=1 << 28), -1),
     (dict(input_kind=2), -1), (dict(pm_bits=8), -1), (dict(terminated=2), -1),
-    (dict(gens=(0o171, 0o135)), -2),
-    (dict(K=9, gens=(0o557, 0o663, 0o711), pm_bits=32), -2),
+    (dict(mapping=3), -1), (dict(lanes_per_pb=3), -1), (dict(lanes_per_pb=16), -1),
+    (dict(mapping=2, lanes_per_pb=2), -1), (dict(mapping=1, lanes_per_pb=64), -1),
+    # the register kernel exists for the registry's generator sets only
+    (dict(gens=(0o171, 0o135), mapping=1), -2), (dict(gens=(0o171, 0o135), lanes_per_pb=2), -2),
+    (dict(K=9, gens=(0o557, 0o663, 0o711), pm_bits=32, mapping=1), -2),
 ])
 def test_create_validation(pbvd, kw, status):
     args = dict(K=7, gens=(0o171, 0o133), D=512, L=42, terminated=True, input_kind=0, pm_bits=16)
@@ -62,6 +65,45 @@ def test_create_validation(pbvd, kw, status):
         pbvd.pbvd_create(**args)
     assert ei.value.status == status
     assert pbvd.pbvd_last_error()
+
+
+@pytest.mark.parametrize("kw", [
+    dict(gens=(0o171, 0o135)),                                   # not in the registry
+    dict(K=9, gens=(0o557, 0o663, 0o711), pm_bits=32),           # register kernel: 16-bit only
+    dict(K=5, gens=(0o31, 0o27, 0o25, 0o23), mapping=2),
+    dict(K=7, gens=(0o171, 0o133), lanes_per_pb=64),
+    dict(K=3, gens=(0o6, 0o3), D=8, L=0, terminated=False, input_kind=1),
+])
+def test_create_any_code_takes_the_wave_mapping(pbvd, kw):
+    """Any generator set in range gets a plan: the state-parallel kernel takes
+    the generators at run time, and every call of such a plan uses it."""
+    args = dict(K=7, gens=(0o171, 0o133), D=512, L=42, terminated=True, input_kind=0, pm_bits=16)
+    args.update(kw)
+    h = pbvd.pbvd_create(**args)
+    try:
+        L = pbvd.lib()
+        for n in (1, 1000, 1 << 22):
+            assert L.pbvd_call_lanes(ctypes.c_void_p(h), n, 0, -(-n // args["D"])) == 64
+    finally:
+        pbvd.pbvd_destroy(h)
+
+
+def test_auto_mapping_rule(pbvd, monkeypatch):
+    """Registered codes: the wave kernel for calls of few PBs, the register
+    kernel (lanes) for many; PBVD_WAVE_MAX_PBS moves the threshold."""
+    L = pbvd.lib()
+    h = pbvd.pbvd_create(7, (0o171, 0o133), 512, 42)
+    try:
+        assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1 << 20, 0, 2048) == 64
+        assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1 << 27, 0, 1 << 18) == 1
+    finally:
+        pbvd.pbvd_destroy(h)
+    monkeypatch.setenv("PBVD_WAVE_MAX_PBS", "0")
+    h = pbvd.pbvd_create(7, (0o171, 0o133), 512, 42)
+    try:
+        assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1 << 20, 0, 2048) in (1, 2)
+    finally:
+        pbvd.pbvd_destroy(h)
 
 
 def test_decode_argument_validation(pbvd):
@@ -164,8 +206,8 @@ def test_call_lanes_choice(pbvd):
     """Lanes per PB: explicit widths are kept, unsupported ones refused, and
     the library's choice follows the documented rule."""
     cases = [(7, (0o171, 0o133), 512, 1 << 27, 1), (7, (0o171, 0o133), 512, 1 << 26, 2),
-             (7, (0o171, 0o133), 512, 1 << 20, 2),
-             (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 8),
+             (7, (0o171, 0o133), 512, 1 << 20, 64),
+             (9, (0o557, 0o663, 0o711), 512, 1 << 27, 2), (9, (0o557, 0o663, 0o711), 512, 1 << 20, 64),
              (5, (0o23, 0o35), 512, 1 << 27, 1), (8, (0o247, 0o371), 64, 64 * 32 * 1024, 2),
              (8, (0o247, 0o371), 64, 64 * 32 * 1000, 4)]
     for K, gens, D, n, want in cases:

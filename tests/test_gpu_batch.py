@@ -226,3 +226,26 @@ def test_batch_failed_set_frames_leaves_empty_batch(torch, pbvd, monkeypatch):
         c = codes[ci]
         ref = oracle.decode(c["K"], c["gens"], c["D"], c["L"], st["syms"], n)["bits"]
         assert np.array_equal(np.unpackbits(host[oo:oo + (n + 7) // 8], bitorder="little")[:n], ref)
+
+
+@pytest.mark.parametrize("mapping", [1, 2], ids=["lanes", "wave"])
+def test_batch_mapping_per_code(torch, pbvd, mapping):
+    """The same frames with every code on the register kernel or on the
+    state-parallel kernel: each frame equals the oracle."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=64, L=42, mapping=mapping),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=96, L=42, mapping=mapping),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=64, L=54, terminated=False, mapping=mapping),
+             dict(K=3, gens=(0o7, 0o5), D=32, L=16, input_kind=1, mapping=mapping)]
+    log("batch mapping %d: 160 frames of four codes, lengths 1..3000" % mapping)
+    check_batch(torch, pbvd, codes, 160, 1, 3000, seed=71 + mapping)
+
+
+def test_batch_codes_outside_the_registry(torch, pbvd):
+    """Codes without a register kernel batch on the state-parallel kernel
+    next to registered ones, in one batch, graph-capturable."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=128, L=42),
+             dict(K=6, gens=(0o53, 0o56, 0o76, 0o64), D=64, L=30),       # not registered
+             dict(K=8, gens=(0o237, 0o350, 0o222), D=96, L=48, terminated=False),  # not registered
+             dict(K=5, gens=(0o31, 0o6), D=40, L=25, input_kind=1)]      # not registered
+    log("batch: registered + unregistered codes, 200 frames")
+    check_batch(torch, pbvd, codes, 200, 1, 2500, seed=81)

@@ -50,13 +50,15 @@ def gpu_bits(torch, out, nbits):
     return np.unpackbits(out.cpu().numpy(), bitorder="little")[:nbits]
 
 
-def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=True, lanes=0):
+def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=True, lanes=0,
+                mapping=0):
     """Decode PBs [pb_first, pb_first+pb_count) on GPU and oracle; compare
     bits, normalized final metrics and (optionally) survivor decisions.
-    lanes: lanes per PB of the plan (0: the library's choice)."""
+    lanes: lanes per PB of the plan (0: the library's choice); mapping:
+    PBVD_MAP_AUTO / LANES / WAVE."""
     K, gens, n, kind = st["K"], st["gens"], st["n"], st["kind"]
     term = st["terminated"]
-    with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes) as plan:
+    with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes, mapping) as plan:
         dsyms = to_dev(torch, st["syms"])
         nbits = plan.out_bits(n, pb_first, pb_count)
         out, fpm = plan.decode_ex(dsyms, n, pb_first, pb_count, want_pm=True)
@@ -74,7 +76,7 @@ def check_range(torch, pbvd, st, D, L, pm_bits, pb_first, pb_count, survivors=Tr
         prev = os.environ.get("PBVD_FOLD_SIMDS")
         os.environ["PBVD_FOLD_SIMDS"] = "1"
         try:
-            with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes) as fplan:
+            with pbvd.Plan(K, gens, D, L, term, kind, pm_bits, lanes, mapping) as fplan:
                 out1, _ = fplan.decode_ex(dsyms, n, pb_first, pb_count)
                 assert np.array_equal(gpu_bits(torch, out1, nbits), ref["bits"]), "bits with folding"
         finally:
@@ -205,14 +207,80 @@ def fuzz_cases():
     return cases
 
 
+@pytest.mark.parametrize("mapping", [1, 2], ids=["lanes", "wave"])
 @pytest.mark.parametrize("case", fuzz_cases(), ids=lambda c: "f%d" % c[0])
-def test_fuzz_parity(torch, pbvd, case):
+def test_fuzz_parity(torch, pbvd, case, mapping):
+    """Both kernels (the register kernel, mapping 1; the state-parallel
+    kernel, mapping 2) on the fuzz cases: bits, final metrics, survivors."""
     i, K, gens, n, D, L, term, kind, pm, ebn0 = case
-    log("fuzz %d: K=%d R=%d n=%d D=%d L=%d term=%d kind=%d pm=%d" % (i, K, len(gens), n, D, L,
-                                                                      term, kind, pm))
+    log("fuzz %d map %d: K=%d R=%d n=%d D=%d L=%d term=%d kind=%d pm=%d" % (i, mapping, K, len(gens), n,
+                                                                             D, L, term, kind, pm))
     st = datagen.make_stream(K, gens, n, ebn0, seed=5000 + i, kind=kind, terminated=term)
     nb = oracle.num_blocks(n, D)
-    check_range(torch, pbvd, st, D, L, pm, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7)
+    check_range(torch, pbvd, st, D, L, pm, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7,
+                mapping=mapping)
+
+
+def _gf2_mod(a, b):
+    db = b.bit_length()
+    while a.bit_length() >= db:
+        a ^= b << (a.bit_length() - db)
+    return a
+
+
+def _gf2_gcd(a, b):
+    while b:
+        a, b = b, _gf2_mod(a, b)
+    return a
+
+
+def random_code_cases():
+    """Generator sets drawn at random (K = 3..9, R = 2..4) and kept when they
+    are not catastrophic (the generators share no polynomial factor but a
+    power of x); at least a third are not "special" (g_{K-1} and g_0 not
+    both set in every generator)."""
+    rng = np.random.default_rng(77)
+    cases, n_special = [], 0
+    while len(cases) < 30:
+        K = int(rng.integers(3, 10))
+        R = int(rng.integers(2, 5))
+        gens = tuple(int(g) for g in rng.integers(1, 1 << K, R))
+        if not any(g >> (K - 1) for g in gens) or len(set(gens)) < R:
+            continue
+        g = 0
+        for x in gens:
+            g = _gf2_gcd(g, x) if g else x
+        if g & (g - 1):  # a factor other than x^k
+            continue
+        special = all((x >> (K - 1)) & 1 and x & 1 for x in gens)
+        if special and n_special >= 20:
+            continue
+        n_special += special
+        n = int(rng.integers(50, 4000))
+        D = int(rng.choice([8, 32, 64, 100, 256, 512]))
+        L = int(rng.choice([0, 3, 5 * K, 6 * K, 100]))
+        term = bool(rng.integers(0, 2))
+        kind = int(rng.integers(0, 2))
+        cases.append((len(cases), K, gens, n, D, L, term, kind))
+    assert sum(1 for c in cases if not all((x >> (c[1] - 1)) & 1 and x & 1 for x in c[2])) >= 10
+    return cases
+
+
+@pytest.mark.parametrize("case", random_code_cases(), ids=lambda c: "r%d" % c[0])
+def test_random_codes_parity(torch, pbvd, case):
+    """Any generator set decodes through the C-ABI (the state-parallel
+    kernel takes the generators at run time): bits, final metrics and
+    survivor decisions equal the oracle's."""
+    i, K, gens, n, D, L, term, kind = case
+    log("random code %d: K=%d gens=%s n=%d D=%d L=%d term=%d kind=%d" % (
+        i, K, tuple(oct(g) for g in gens), n, D, L, term, kind))
+    # outside the registry: no register kernel exists for it
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Plan(K, gens, D, L, term, kind, 16, 0, pbvd.PBVD_MAP_LANES)
+    assert ei.value.status == pbvd.PBVD_ENOTSUP
+    st = datagen.make_stream(K, gens, n, 1.5, seed=7000 + i, kind=kind, terminated=term)
+    nb = oracle.num_blocks(n, D)
+    check_range(torch, pbvd, st, D, L, 16, 0, nb, survivors=nb * (D + L) * (1 << (K - 1)) < 4e7)
 
 
 def lane_cases():
@@ -385,13 +453,15 @@ def test_workspace_chunking(torch, pbvd, monkeypatch):
     assert np.array_equal(got, ref)
     # with the stream-end PBs folded into wave 0 of the first launch
     monkeypatch.setenv("PBVD_FOLD_SIMDS", "1")
-    for lanes in (1, 2):
+    for lanes in (1, 2, 64):
         with pbvd.Plan(7, (0o171, 0o133), 512, 42, lanes_per_pb=lanes) as plan:
             got = gpu_bits(torch, plan.decode(dsyms, n), n)
         assert np.array_equal(got, ref), "lanes %d" % lanes
+    assert np.array_equal(ref, oracle.decode(7, (0o171, 0o133), 512, 42, st["syms"], n,
+                                             nthreads=NTHREADS)["bits"])
 
 
-@pytest.mark.parametrize("lanes", [1, 2])
+@pytest.mark.parametrize("lanes", [1, 2, 64])
 def test_huge_stream_tail_window(torch, pbvd, lanes):
     """The last 80 PBs of a 2^34-bit stream (64-bit stage, symbol and output
     offsets), with only their symbols resident: the decoder is given a base

@@ -142,3 +142,23 @@ def test_server_admission_counts_every_best_state_block(pbvd):
     assert max(i["batch_frames"] for _, i in res) > 8
     for (ci, st), (out, _) in zip(reqs, res):
         assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st))
+
+
+def test_server_wave_mapping_and_unregistered_code(pbvd):
+    """A server whose codes run on the state-parallel kernel (one explicitly,
+    one because it has no register kernel) next to a register-kernel code:
+    every request equals the oracle and decoding it alone."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=64, L=42, mapping=pbvd.PBVD_MAP_WAVE),
+             dict(K=8, gens=(0o237, 0o350, 0o222), D=64, L=48),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=64, L=54)]
+    reqs = datagen.make_requests(codes, 90, seed=506, median=500, hi=5000)
+    log("server: wave mapping + unregistered code, 90 requests")
+    with pbvd.Server(codes, device_bytes=128 << 20, max_inflight=3, max_batch_frames=32) as srv:
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        mixed = [srv.wait(t) for t in tickets]
+        alone = [srv.wait(srv.submit(ci, st["syms"], st["n"])) for ci, st in reqs[:20]]
+    for (ci, st), (out, _) in zip(reqs, mixed):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st)), \
+            "request of %d bits (code %d) differs from the oracle" % (st["n"], ci)
+    for (m, _), (a, _) in zip(mixed[:20], alone):
+        assert np.array_equal(m, a)
