@@ -62,15 +62,26 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
     for name in ("pbvd_capi", "pbvd_batch", "pbvd_server", "pbvd_aux"):
         units.append((os.path.join(csrc, name + ".hip"), os.path.join(build_dir, name + ".o"), []))
 
-    # a unit depends on its own source and on every header
-    headers = [os.path.join(csrc, f) for f in os.listdir(csrc) if f.endswith(".hpp")]
-    headers.append(os.path.join(INCLUDE, "pbvd.h"))
-    newest_header = max(os.path.getmtime(h) for h in headers)
+    def newest_dep(src):
+        """Latest modification time of a source and the local headers it
+        includes (directly or not)."""
+        seen, stack, t = set(), [src], 0.0
+        while stack:
+            f = stack.pop()
+            if f in seen or not os.path.exists(f):
+                continue
+            seen.add(f)
+            t = max(t, os.path.getmtime(f))
+            with open(f) as fh:
+                for name in re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), flags=re.M):
+                    for d in (csrc, INCLUDE):
+                        stack.append(os.path.join(d, name))
+        return t
 
     def compile_unit(u):
         src, obj, extra = u
         if (incremental and not defines and os.path.exists(obj)
-                and os.path.getmtime(obj) > max(newest_header, os.path.getmtime(src))):
+                and os.path.getmtime(obj) > newest_dep(src)):
             return obj
         _run([HIPCC, *COMMON[:-2], *flags, *extra, "-c", src, "-o", obj])
         if verbose:

@@ -6,7 +6,7 @@
 
 #include "pbvd_aux.hpp"
 #include "pbvd_kernel.hpp"
-#include "pbvd_wave.hpp"
+#include "pbvd_wave_args.hpp"
 
 namespace pbvd {
 namespace {

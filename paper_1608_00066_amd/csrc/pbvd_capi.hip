@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 
 #include "pbvd.h"
@@ -309,17 +310,38 @@ namespace {
 
 // Device scratch of one decode in flight: survivor rows of one launch and the
 // output staging words (used when D % 32 != 0 or the output is unaligned).
+// A fixed workspace is carved from the library's static scratch: it is
+// never grown or freed, and a call that needs more fails.
 struct Workspace {
     uint32_t *sp = nullptr;
     size_t sp_bytes = 0;
     uint32_t *words = nullptr;
     size_t words_bytes = 0;
+    bool fixed = false;
 };
 
 void free_workspace(Workspace &w) {
-    if (w.sp) (void)hipFree(w.sp);
-    if (w.words) (void)hipFree(w.words);
+    if (!w.fixed) {
+        if (w.sp) (void)hipFree(w.sp);
+        if (w.words) (void)hipFree(w.words);
+    }
     w = Workspace{};
+}
+
+// Survivor area / output staging of at least `need` bytes.
+pbvd_status ws_survivors(Workspace &ws, size_t need) {
+    if (!ws.fixed) return ensure_buffer(&ws.sp, &ws.sp_bytes, need, "survivors");
+    if (need > ws.sp_bytes)
+        return fail(PBVD_EINVAL, "survivors of one launch need %zu bytes, the static scratch has %zu", need,
+                    ws.sp_bytes);
+    return PBVD_OK;
+}
+pbvd_status ws_staging(Workspace &ws, size_t need) {
+    if (!ws.fixed) return ensure_buffer(&ws.words, &ws.words_bytes, need, "output staging");
+    if (need > ws.words_bytes)
+        return fail(PBVD_EINVAL, "output staging needs %zu bytes, the static scratch has %zu", need,
+                    ws.words_bytes);
+    return PBVD_OK;
 }
 
 constexpr int kMaxPipeStreams = 8;
@@ -340,6 +362,40 @@ struct PipeStream {
 
 }  // namespace
 
+namespace {
+
+// Static device scratch of pbvd_decode_ex_noalloc: survivor rows and output
+// staging for callers that cannot allocate.  Every device the library runs
+// on holds one copy from the moment the library's code object is loaded
+// until the process ends; calls on one device share it.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+__device__ __align__(256) uint32_t scratch[kStaticScratchBytes / 4];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current: looked
+// up once per device (the array's name is a host-side stand-in, not an
+// address the kernels can use).
+pbvd_status static_scratch(int dev, uint32_t **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(PBVD_EINVAL, "device %d outside [0, %d)", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail_hip(e == hipSuccess ? hipErrorInvalidSymbol : e, "static scratch address");
+        }
+        g_scratch_ptr[dev] = (uint32_t *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return PBVD_OK;
+}
+
+}  // namespace
+
 struct pbvd_plan {
     pbvd_code code;
     int code_idx;             // register kernel's registry index, -1: none
@@ -355,9 +411,14 @@ struct pbvd_plan {
 
 namespace {
 
-int64_t waves_per_launch(const pbvd_plan *p, int64_t sp_wave_dwords) {
+// Waves (or PBs of the wave kernel) of one launch: as many survivor slots of
+// sp_wave_dwords as the budget holds, at least one; a fixed workspace holds
+// what fits it (possibly none).
+int64_t launch_limit(const pbvd_plan *p, const Workspace &ws, int64_t sp_wave_dwords) {
     int64_t w = p->budget_bytes / (sp_wave_dwords * 4);
-    return w < 1 ? 1 : w;
+    if (w < 1) w = 1;
+    if (ws.fixed) w = std::min<int64_t>(w, (int64_t)(ws.sp_bytes / (size_t)(sp_wave_dwords * 4)));
+    return w;
 }
 
 // Lanes per PB of one call: the code's choice, or else
@@ -406,13 +467,16 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
     }
     if (pb_count == 0) return PBVD_OK;
     const int64_t slot = wave_slot_dwords(c);
-    const int64_t per_launch = std::max<int64_t>(1, p->budget_bytes / (slot * 4));
+    const int64_t per_launch = launch_limit(p, ws, slot);
+    if (per_launch < 1)
+        return fail(PBVD_EINVAL, "one PB's survivors (%lld bytes) do not fit the static scratch",
+                    (long long)(slot * 4));
     if (single_launch && pb_count > per_launch)
         return fail(PBVD_EINVAL, "%lld PBs do not fit one launch (limit %lld)", (long long)pb_count,
                     (long long)per_launch);
     if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
     const int64_t launch_pbs = std::min(pb_count, per_launch);
-    pbvd_status st = ensure_buffer(&ws.sp, &ws.sp_bytes, (size_t)(launch_pbs * slot * 4), "survivors");
+    pbvd_status st = ws_survivors(ws, (size_t)(launch_pbs * slot * 4));
     if (st != PBVD_OK) return st;
     const int64_t end_bit = std::min(n_bits, (pb_first + pb_count) * D);
     const int64_t out_bits = end_bit - pb_first * D;
@@ -420,7 +484,7 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
     const bool direct = (D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
     if (!direct) {
         const int64_t nwords = ceil_div(out_bits, 32) + 2;
-        st = ensure_buffer(&ws.words, &ws.words_bytes, (size_t)nwords * 4, "output staging");
+        st = ws_staging(ws, (size_t)nwords * 4);
         if (st != PBVD_OK) return st;
         hipError_t e = pbvd::fill_u32(ws.words, nwords, 0u, stream);
         if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
@@ -479,22 +543,24 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
     if (geo_out) *geo_out = g;
     if (lb_out) *lb_out = lb;
     if (pb_count == 0) return PBVD_OK;
-    const int64_t per_launch = waves_per_launch(p, sp_wave_dwords);
+    const int64_t per_launch = launch_limit(p, ws, sp_wave_dwords);
+    if (per_launch < 1)
+        return fail(PBVD_EINVAL, "one wave's survivors (%lld bytes) do not fit the static scratch",
+                    (long long)(sp_wave_dwords * 4));
     if (single_launch && g.n_waves > per_launch)
         return fail(PBVD_EINVAL, "%lld waves do not fit one launch (limit %lld)",
                     (long long)g.n_waves, (long long)per_launch);
     if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
 
     const int64_t launch_waves = g.n_waves < per_launch ? g.n_waves : per_launch;
-    pbvd_status st = ensure_buffer(&ws.sp, &ws.sp_bytes,
-                                   (size_t)(launch_waves * sp_wave_dwords * 4), "survivors");
+    pbvd_status st = ws_survivors(ws, (size_t)(launch_waves * sp_wave_dwords * 4));
     if (st != PBVD_OK) return st;
 
     const int64_t out_bytes = ceil_div(g.out_bits, 8);
     const bool direct = (c.D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
     if (!direct) {
         const int64_t nwords = ceil_div(g.out_bits, 32) + 2;
-        st = ensure_buffer(&ws.words, &ws.words_bytes, (size_t)nwords * 4, "output staging");
+        st = ws_staging(ws, (size_t)nwords * 4);
         if (st != PBVD_OK) return st;
         hipError_t e = pbvd::fill_u32(ws.words, nwords, 0u, stream);
         if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
@@ -571,6 +637,13 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
     // once a call has enough PBs to fill the device with lanes
     p->wave_max_pbs = c.K <= 7 ? 16384 : 8192;
     if (const char *env = getenv("PBVD_WAVE_MAX_PBS")) p->wave_max_pbs = atoll(env);
+    {
+        // set up the static scratch of this device (pbvd_decode_ex_noalloc);
+        // a failure here is reported by that call, which tries again
+        uint32_t *unused = nullptr;
+        DeviceGuard dg(p->device);
+        if (dg.ok && static_scratch(p->device, &unused) != PBVD_OK) g_last_error[0] = 0;
+    }
     // PBVD_FOLD_SIMDS overrides the SIMD count of the edge-folding rule
     // (1: fold whenever it saves a wave, 0: never fold)
     if (const char *env = getenv("PBVD_FOLD_SIMDS")) p->n_simd = atoll(env) < 0 ? 0 : atoll(env);
@@ -587,6 +660,37 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
     DeviceGuard dg(p->device);
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
     return run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, d_final_pm,
+                      (hipStream_t)hip_stream, nullptr, false);
+}
+
+pbvd_status pbvd_decode_ex_noalloc(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                                   int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
+                                   void *hip_stream) {
+    g_last_error[0] = 0;
+    pbvd_status st = validate_call(p, d_syms, n_bits, pb_first, pb_count, d_out_bits);
+    if (st != PBVD_OK || pb_count == 0) return st;
+    DeviceGuard dg(p->device);
+    if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", p->device);
+    uint32_t *base = nullptr;
+    st = static_scratch(p->device, &base);
+    if (st != PBVD_OK) return st;
+    // [output staging (only for unaligned output) | survivor rows]
+    const int64_t D = p->code.D;
+    const int64_t end_bit = std::min(n_bits, (pb_first + pb_count) * D);
+    const int64_t out_bits = end_bit - pb_first * D;
+    const bool direct = (D % 32 == 0) && (((uintptr_t)d_out_bits & 3u) == 0);
+    const size_t staging = direct ? 0 : (size_t)ceil_div((ceil_div(out_bits, 32) + 2) * 4, 256) * 256;
+    if (staging >= kStaticScratchBytes)
+        return fail(PBVD_EINVAL, "output staging of %lld bits needs %zu bytes, more than the %zu-byte static "
+                                 "scratch (use a 4-byte aligned output and D %% 32 == 0, or pbvd_decode_ex)",
+                    (long long)out_bits, staging, kStaticScratchBytes);
+    Workspace ws;
+    ws.fixed = true;
+    ws.words = base;
+    ws.words_bytes = staging;
+    ws.sp = base + staging / 4;
+    ws.sp_bytes = kStaticScratchBytes - staging;
+    return run_decode(p, ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, d_final_pm,
                       (hipStream_t)hip_stream, nullptr, false);
 }
 

@@ -6,7 +6,7 @@
 #include <stdint.h>
 
 #include "pbvd_kernel.hpp"
-#include "pbvd_wave.hpp"
+#include "pbvd_wave_args.hpp"
 
 // X(index, K, R, g0, g1, g2, g3): generators in octal, gen[r] bit k = g_k.
 // The first four are the codes of the benchmark workloads; the others are

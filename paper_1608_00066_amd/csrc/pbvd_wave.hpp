@@ -50,38 +50,10 @@
 #include <type_traits>
 
 #include "pbvd_kernel.hpp"
+#include "pbvd_wave_args.hpp"
 
 namespace pbvd {
 namespace wave {
-
-// Stages per survivor dword: a whole number of phase cycles.
-__host__ __device__ constexpr int trip_stages(int V) { return V * (32 / V); }
-// Register slots per lane (2^V states over 64 lanes).
-__host__ __device__ constexpr int slots(int V) { return V > 6 ? 1 << (V - 6) : 1; }
-// Survivor dwords of one PB of len forward stages.
-__host__ __device__ constexpr int64_t pb_dwords(int V, int64_t len) {
-    return (len + trip_stages(V) - 1) / trip_stages(V) * slots(V) * kWave;
-}
-
-struct Args {
-    const uint8_t *syms;     // symbols; stream mode: stage 0 of the stream
-    const uint8_t *in_end;   // end of the readable symbol bytes
-    uint8_t *out;            // packed decoded bits
-    uint32_t *out_words;     // zeroed word staging (atomic output) or null
-    int64_t out_bytes;       // bytes of `out` (direct output bound)
-    int32_t *final_pm;       // [PB][2^V] normalized final metrics or null
-    uint32_t *sp;            // survivor scratch, sp_wave_dwords per wave
-    int64_t sp_wave_dwords;
-    // stream mode (descs == null): PBs [pb_first + wave_begin, + n_waves)
-    int64_t n, T, pb_first;
-    int32_t D, L, terminated;
-    int32_t out_mode;        // kOutDirect / kOutAtomic / kOutBytes
-    // tile mode: one descriptor per PB (lane descriptor of the batch work list)
-    const LaneDesc *descs;
-    int64_t wave_begin;      // first PB of this launch (relative to pb_first / descs)
-    int64_t n_waves;         // PBs of this launch
-    uint32_t gen[4];         // generators (gen[r] bit k = g_k of Eq. 2), 0 past R
-};
 
 // Even and odd position's value of the pair whose bit is lane bit B.
 template <int B>
@@ -112,15 +84,19 @@ __device__ __forceinline__ void pair_values(int v, int &e, int &o) {
     }
 }
 
-// acc + (dot product of the symbol dword of lane LANE of the row and mask):
-// v_dot4c_i32_i8 with the symbols broadcast by DPP row_newbcast (written out:
-// the compiler does not fold the broadcast into the dot product).
+// up += dot(q of lane LANE of the row, mu); lo += dot(q of lane LANE, ml):
+// v_dot4c_i32_i8 with the symbol dword broadcast by DPP row_newbcast (written
+// out: the compiler does not fold the broadcast into the dot product).  A
+// dot product's result may be read by another vector instruction only three
+// wait states after it is written, so the pair ends with s_nop 2 (the
+// compiler cannot see into the statement to insert them).
 template <int LANE>
-__device__ __forceinline__ int dot_bcast(int acc, uint32_t qv, uint32_t mask) {
-    asm("v_dot4c_i32_i8_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
-        : "+v"(acc)
-        : "v"(qv), "v"(mask), "n"(LANE));
-    return acc;
+__device__ __forceinline__ void dot_pair(int &up, int &lo, uint32_t q, uint32_t mu, uint32_t ml) {
+    asm("v_dot4c_i32_i8_dpp %0, %2, %3 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+        "v_dot4c_i32_i8_dpp %1, %2, %4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+        "s_nop 2"
+        : "+v"(up), "+v"(lo)
+        : "v"(q), "v"(mu), "v"(ml), "n"(LANE));
 }
 
 // acc << 1 | (diff's sign bit)
@@ -268,10 +244,9 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         if constexpr (PH < LB) {
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
-                int e, o;
-                pair_values<PH>(pm[s], e, o);
-                const int up = dot_bcast<k % 16>(e, q, mup[PH][s]);
-                const int lo = dot_bcast<k % 16>(o, q, mlo[PH][s]);
+                int up, lo;
+                pair_values<PH>(pm[s], up, lo);
+                dot_pair<k % 16>(up, lo, q, mup[PH][s], mlo[PH][s]);
                 acc[s] = push_sign(acc[s], lo - up);
                 pm[s] = min(up, lo);
             }
@@ -280,11 +255,9 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
                 if (s & M) continue;
-                const int e = pm[s], o = pm[s | M];
-                const int up0 = dot_bcast<k % 16>(e, q, mup[PH][s]);
-                const int lo0 = dot_bcast<k % 16>(o, q, mlo[PH][s]);
-                const int up1 = dot_bcast<k % 16>(e, q, mup[PH][s | M]);
-                const int lo1 = dot_bcast<k % 16>(o, q, mlo[PH][s | M]);
+                int up0 = pm[s], lo0 = pm[s | M], up1 = pm[s], lo1 = pm[s | M];
+                dot_pair<k % 16>(up0, lo0, q, mup[PH][s], mlo[PH][s]);
+                dot_pair<k % 16>(up1, lo1, q, mup[PH][s | M], mlo[PH][s | M]);
                 acc[s] = push_sign(acc[s], lo0 - up0);
                 acc[s | M] = push_sign(acc[s | M], lo1 - up1);
                 pm[s] = min(up0, lo0);
