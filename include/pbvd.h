@@ -304,9 +304,11 @@ typedef struct {
 } pbvd_request_info;
 
 /* Create a server for n_codes (1..16) code/block parameter sets (each valid
- * for pbvd_batch_create) on the current device.  Allocates the device budget
- * and pinned staging buffers and starts the worker thread (which polls for
- * 2 ms after its last work before it sleeps, to admit requests quickly). */
+ * for pbvd_batch_create) on the current device.  Codes that leave the mapping
+ * to the library (PBVD_MAP_AUTO, lanes_per_pb 0) decode on the wave mapping,
+ * the lowest latency per request.  Allocates the device budget and pinned
+ * staging buffers and starts the worker thread (which polls for 2 ms after
+ * its last work before it sleeps, to admit requests quickly). */
 pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pbvd_server_config *cfg,
                                pbvd_server **out);
 

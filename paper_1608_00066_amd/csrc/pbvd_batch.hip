@@ -31,7 +31,8 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
         cs.idx[i] = idx;
         const int req = requested_lb(codes[i]);
         const int top = max_lb(codes[i]);
-        cs.lb[i] = idx < 0 ? kWaveLb : req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
+        cs.lb[i] = idx < 0 || (req < 0 && auto_lb == kWaveLb) ? kWaveLb
+                   : req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
     }
     cs.n = n;
     *out = cs;

@@ -78,8 +78,9 @@ struct CodeSet {
 
 // Validates n codes for batched use (D % 8 == 0) into *out.  Codes that let
 // the library choose their lanes per PB get auto_lb (clipped to what the
-// code supports; -1: the largest it supports); codes without a register
-// kernel, or that ask for the wave mapping, get kWaveLb.
+// code supports; -1: the largest it supports; kWaveLb: the wave mapping);
+// codes without a register kernel, or that ask for the wave mapping, get
+// kWaveLb.
 pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int auto_lb = 0);
 
 // The work of one code: tiles of the register kernel (waves of 64 >> lb

@@ -412,8 +412,9 @@ pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pb
     if (cfg->device_bytes < ((int64_t)cfg->max_inflight << 20))
         return fail(PBVD_EINVAL, "device_bytes must be at least 1 MiB per batch in flight");
     CodeSet cs;
-    // latency first: codes that leave it open get the largest lane group
-    pbvd_status st = make_code_set(codes, n_codes, &cs, -1);
+    // latency first: codes that leave the mapping to the library decode on
+    // the state-parallel kernel (a PB 64 lanes wide)
+    pbvd_status st = make_code_set(codes, n_codes, &cs, kWaveLb);
     if (st != PBVD_OK) return st;
     pbvd_server *sv = new (std::nothrow) pbvd_server();
     if (!sv) return fail(PBVD_ENOMEM, "host allocation failed");
