@@ -150,6 +150,28 @@ pbvd_status pbvd_decode_ex(pbvd_plan *p, const void *d_syms, int64_t n_bits, int
                            int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
                            void *hip_stream);
 
+/* pbvd_decode_ex for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc while
+ * decoding.  It calls no hipMalloc, hipFree or allocating library routine:
+ * the survivor rows and the output staging of the call live in a static
+ * device array of the library (PBVD_STATIC_SCRATCH_BYTES), which every
+ * device the library runs on holds from the moment the library's code
+ * object is loaded until the process ends (its address is looked up once
+ * per device, by pbvd_create or by the first call).  Arguments, layout,
+ * bits and final metrics are those of pbvd_decode_ex; a stream whose
+ * survivors do not fit one launch is decoded in several launches that reuse
+ * the array.  PBVD_EINVAL (nothing decoded) when the output staging -- 4
+ * bytes per 32 decoded bits plus 8, only when D % 32 != 0 or d_out_bits is
+ * not 4-byte aligned -- together with the survivors of one wave (one PB for
+ * the wave mapping) exceeds the array.  Every call on a device shares that
+ * device's array and leaves its contents behind: calls that overlap on one
+ * device (other streams, other threads, other plans) race and must be
+ * serialized by the caller. */
+#define PBVD_STATIC_SCRATCH_BYTES (64u << 20)
+pbvd_status pbvd_decode_ex_noalloc(pbvd_plan *p, const void *d_syms, int64_t n_bits, int64_t pb_first,
+                                   int64_t pb_count, uint8_t *d_out_bits, int32_t *d_final_pm,
+                                   void *hip_stream);
+
 /* pbvd_decode_host flag: both host buffers are page-locked (e.g. from
  * hipHostMalloc), so chunks are copied by DMA straight from and to them. */
 #define PBVD_HOST_PINNED 1u

@@ -368,7 +368,7 @@ namespace {
 // staging for callers that cannot allocate.  Every device the library runs
 // on holds one copy from the moment the library's code object is loaded
 // until the process ends; calls on one device share it.
-constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr size_t kStaticScratchBytes = PBVD_STATIC_SCRATCH_BYTES;
 __device__ __align__(256) uint32_t scratch[kStaticScratchBytes / 4];
 
 constexpr int kMaxDevices = 64;

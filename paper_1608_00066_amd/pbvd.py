@@ -69,6 +69,7 @@ SIGNATURES = {
     "pbvd_create": (_I32, [ctypes.POINTER(pbvd_code), ctypes.POINTER(_P)]),
     "pbvd_decode": (_I32, [_P, _P, _I64, _P, _P]),
     "pbvd_decode_ex": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
+    "pbvd_decode_ex_noalloc": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
     "pbvd_decode_host": (_I32, [_P, _P, _I64, _P, _I32, _I64, ctypes.c_uint32]),
     "pbvd_num_blocks": (_I64, [_P, _I64]),
     "pbvd_call_lanes": (_I32, [_P, _I64, _I64, _I64]),
