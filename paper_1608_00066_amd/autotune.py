@@ -41,8 +41,9 @@ def time_batch(torch, codes, frames, syms_dev, out_dev, reps: int = 5, warmup: i
 
 def lanes_allowed(code, lanes: int) -> bool:
     """Lane-group widths the library supports for a code (16-bit metrics,
-    at least 16 packed registers per lane)."""
-    if lanes == 1:
+    at least 16 packed registers per lane; 64 lanes, the state-parallel
+    mapping, takes any code)."""
+    if lanes in (1, 64):
         return True
     return (code.get("pm_bits", 16) == 16 and lanes in (2, 4, 8)
             and (1 << (code["K"] - 2)) // lanes >= 16)
@@ -50,9 +51,11 @@ def lanes_allowed(code, lanes: int) -> bool:
 
 def tune_batch_d(torch, codes, frames, syms_dev, out_dev,
                  d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512),
-                 lane_candidates=(1, 2), reps: int = 5):
+                 lane_candidates=(1, 2, 64), reps: int = 5):
     """One D for all codes and one lane-group width per run (codes that do
-    not support it keep one lane), the fastest batched decode of `frames`.
+    not support it keep one lane; 64: the state-parallel kernel, one
+    persistent launch for all codes of one K), the fastest batched decode of
+    `frames`.
     Returns (codes with D and lanes_per_pb filled in, [((D, lanes), seconds,
     info)])."""
     table = []

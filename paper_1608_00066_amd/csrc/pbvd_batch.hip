@@ -1,9 +1,13 @@
 // Batched decoding (pbvd_batch_* of include/pbvd.h): the work-list builder
 // that packs the parallel blocks of many frames into waves, and the batch
-// object that uploads it once and launches one kernel per code, the codes
-// on forked streams so their launches overlap on the device.
+// object that uploads it once and launches, per decode, one tile kernel per
+// register-kernel code and one persistent state-parallel kernel per
+// constraint length (all its codes in one launch), these launch units on
+// forked streams so that they overlap on the device.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <stdlib.h>
 
 #include <algorithm>
 #include <new>
@@ -11,6 +15,7 @@
 #include <vector>
 
 #include "pbvd.h"
+#include "pbvd_aux.hpp"
 #include "pbvd_host.hpp"
 #include "pbvd_registry.hpp"
 
@@ -50,7 +55,7 @@ struct PbRec {
 }  // namespace
 
 pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
-                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl) {
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves) {
     std::vector<std::vector<PbRec>> per_code(cs.n);
     std::vector<std::pair<int64_t, int64_t>> outs;
     outs.reserve((size_t)n_frames);
@@ -99,13 +104,39 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
     wl->lanes.clear();
     wl->heads.clear();
     wl->descs.clear();
+    for (FusedGroup &fg : wl->fused) fg = FusedGroup{};
+    if (fuse_waves) {
+        // one descriptor list per K over all its state-parallel codes, the
+        // longest PBs first (the persistent waves take them in this order,
+        // so the longest finish first and the short ones fill the tail)
+        for (int K = kMinK; K <= kMaxK; ++K) {
+            FusedGroup &fg = wl->fused[K - kMinK];
+            std::vector<PbRec> v;
+            for (int ci = 0; ci < cs.n; ++ci) {
+                if (cs.lb[ci] != kWaveLb || cs.codes[ci].K != K) continue;
+                const int slot = fg.n_codes++;
+                fg.codes[slot] = ci;
+                fg.sp_wave_dwords = std::max(fg.sp_wave_dwords, wave_slot_dwords(cs.codes[ci]));
+                for (PbRec r : per_code[ci]) {
+                    r.flags |= slot << pbvd::wave::kDescCodeShift;
+                    v.push_back(r);
+                }
+                per_code[ci].clear();
+            }
+            std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) { return x.len > y.len; });
+            fg.desc_begin = (int64_t)wl->descs.size();
+            fg.n_descs = (int64_t)v.size();
+            for (const PbRec &r : v)
+                wl->descs.push_back(pbvd::LaneDesc{r.sym, r.out_bit, r.len, r.store0, r.dec_end, r.flags});
+        }
+    }
     for (int ci = 0; ci < cs.n; ++ci) {
         const pbvd_code &c = cs.codes[ci];
         const int64_t U = pbvd::trip_stages(c.K);
         const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
         const int lb = cs.lb[ci];
         if (lb == kWaveLb) {
-            // one wave per PB, longest first
+            // one wave per PB, longest first (fused: already listed, empty here)
             std::vector<PbRec> &v = per_code[ci];
             std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) { return x.len > y.len; });
             wl->groups[ci].tile_begin = (int64_t)wl->descs.size();
@@ -193,9 +224,7 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
         a.sp = sp;
         a.sp_wave_dwords = g.sp_wave_dwords;
         a.descs = d_descs + g.tile_begin;
-        for (int r = 0; r < 4; ++r) a.gen[r] = r < c.R ? c.gen[r] : 0u;
-        req.R = c.R;
-        req.input_kind = c.input_kind;
+        a.codes[0] = wave_code(c);
         req.stream = stream;
         const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
         for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
@@ -231,6 +260,34 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
     return PBVD_OK;
 }
 
+pbvd_status launch_fused(const CodeSet &cs, int K, const FusedGroup &g, const uint8_t *d_syms,
+                         int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_descs, uint32_t *sp,
+                         int64_t waves, uint32_t *counter, hipStream_t stream) {
+    if (g.n_descs == 0) return PBVD_OK;
+    // a kernel, not a memset node: the launch may be captured into a graph
+    hipError_t e = pbvd::fill_u32(counter, pbvd::wave::kCounters * pbvd::wave::kCounterStride, 0u, stream);
+    if (e != hipSuccess) return fail_hip(e, "work counter reset");
+    pbvd::WaveLaunchRequest req{};
+    pbvd::wave::Args &a = req.args;
+    a.syms = d_syms;
+    a.in_end = d_syms + sym_bytes;
+    a.out = d_out;
+    a.out_mode = pbvd::kOutBytes;
+    a.sp = sp;
+    a.sp_wave_dwords = g.sp_wave_dwords;
+    a.descs = d_descs + g.desc_begin;
+    a.counter = counter;
+    a.n_items = g.n_descs;
+    for (int k = 0; k < g.n_codes; ++k) a.codes[k] = wave_code(cs.codes[g.codes[k]]);
+    a.wave_begin = 0;
+    a.n_waves = std::max<int64_t>(1, std::min(waves, g.n_descs));
+    req.grid = (unsigned)ceil_div(a.n_waves, pbvd::kBlockThreads / pbvd::kWave);
+    req.stream = stream;
+    e = launch_wave(K, req);
+    if (e != hipSuccess) return fail_hip(e, "persistent wave kernel launch");
+    return PBVD_OK;
+}
+
 }  // namespace pbvd_host
 
 using namespace pbvd_host;
@@ -241,6 +298,12 @@ struct pbvd_batch {
     TileGroup groups[kMaxCodes];
     int64_t per_launch[kMaxCodes];  // waves per launch of each code
     int64_t sp_off[kMaxCodes];      // dword offset of each code's survivor area
+    // state-parallel codes: one persistent launch per K
+    FusedGroup fused[kMaxK - kMinK + 1];
+    int64_t fused_waves[kMaxK - kMinK + 1];
+    int64_t fused_sp_off[kMaxK - kMinK + 1];
+    uint32_t *counters = nullptr;   // the work counters of each K, kCounterDwords apart
+    size_t counters_bytes = 0;
     int64_t n_tiles = 0, n_blocks = 0, n_stages = 0;
     int64_t sym_bytes = 0, out_bytes = 0;
     pbvd::LaneDesc *d_lanes = nullptr;
@@ -249,8 +312,9 @@ struct pbvd_batch {
     size_t lanes_bytes = 0, heads_bytes = 0, descs_bytes = 0;
     uint32_t *sp = nullptr;
     size_t sp_bytes = 0;
-    // codes after the first run on these streams, forked from and joined to
-    // the caller's stream with events
+    // launch units (a code's tiles, or a K's persistent launch) after the
+    // first run on these streams, forked from and joined to the caller's
+    // stream with events
     hipStream_t aux[kMaxCodes] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kMaxCodes] = {};
@@ -262,13 +326,16 @@ struct pbvd_batch {
 
 namespace {
 
+constexpr int64_t kCounterDwords = pbvd::wave::kCounters * pbvd::wave::kCounterStride;
+
 void release(pbvd_batch *b) {
     DeviceGuard dg(b->device);
-    if (b->sp || b->d_lanes || b->d_heads || b->d_descs) (void)hipDeviceSynchronize();
+    if (b->sp || b->d_lanes || b->d_heads || b->d_descs || b->counters) (void)hipDeviceSynchronize();
     if (b->sp) (void)hipFree(b->sp);
     if (b->d_lanes) (void)hipFree(b->d_lanes);
     if (b->d_heads) (void)hipFree(b->d_heads);
     if (b->d_descs) (void)hipFree(b->d_descs);
+    if (b->counters) (void)hipFree(b->counters);
     for (int i = 0; i < kMaxCodes; ++i) {
         if (b->aux[i]) (void)hipStreamDestroy(b->aux[i]);
         if (b->join[i]) (void)hipEventDestroy(b->join[i]);
@@ -317,7 +384,7 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     WorkList wl;
     pbvd_status st;
     try {
-        st = build_work_list(cs, frames, n_frames, sym_bytes, out_bytes, &wl);
+        st = build_work_list(cs, frames, n_frames, sym_bytes, out_bytes, &wl, true);
     } catch (...) {
         st = fail(PBVD_ENOMEM, "host allocation failed while building the work list");
     }
@@ -338,6 +405,7 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     b->n_blocks = 0;
     b->n_stages = 0;
     for (int ci = 0; ci < kMaxCodes; ++ci) b->groups[ci] = TileGroup{};
+    for (FusedGroup &fg : b->fused) fg = FusedGroup{};
     {
         // streams and events of the fork, made once, outside any capture
         hipError_t e = hipSuccess;
@@ -351,10 +419,24 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     }
     // survivor areas: each code gets its own (codes run concurrently); all of
     // a code's tiles in one launch when the budget allows, else the budget is
-    // split evenly between the codes and their launches reuse their area
+    // split evenly between the codes and their launches reuse their area.  A
+    // persistent launch needs an area per resident wave only, whatever its
+    // PB count (fewer waves when the budget is short).
     const int64_t budget = workspace_budget_bytes();
+    int64_t fused_waves[kMaxK - kMinK + 1] = {};
     int64_t full = 0;
     for (int ci = 0; ci < b->cs.n; ++ci) full += wl.groups[ci].n_tiles * wl.groups[ci].sp_wave_dwords * 4;
+    for (int K = kMinK; K <= kMaxK; ++K) {
+        const FusedGroup &fg = wl.fused[K - kMinK];
+        if (fg.n_descs == 0) continue;
+        int64_t res = resident_waves(K);
+        if (res <= 0) return fail(PBVD_EHIP, "occupancy query of the K=%d persistent kernel failed", K);
+        // PBVD_PERSISTENT_WAVES caps the waves (tests: many PBs per wave)
+        if (const char *env = getenv("PBVD_PERSISTENT_WAVES"))
+            if (atoll(env) > 0) res = std::min<int64_t>(res, atoll(env));
+        fused_waves[K - kMinK] = std::min(fg.n_descs, res);
+        full += fused_waves[K - kMinK] * fg.sp_wave_dwords * 4;
+    }
     int64_t per_launch[kMaxCodes], sp_off[kMaxCodes], total = 0;
     for (int ci = 0; ci < b->cs.n; ++ci) {
         const TileGroup &g = wl.groups[ci];
@@ -364,6 +446,18 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
         sp_off[ci] = total;
         total += g.n_tiles > 0 ? per_launch[ci] * g.sp_wave_dwords : 0;
     }
+    int64_t fused_sp_off[kMaxK - kMinK + 1] = {};
+    for (int K = kMinK; K <= kMaxK; ++K) {
+        const FusedGroup &fg = wl.fused[K - kMinK];
+        int64_t &w = fused_waves[K - kMinK];
+        if (fg.n_descs == 0) continue;
+        if (full > budget) w = std::min(w, std::max<int64_t>(1, budget / b->cs.n / (fg.sp_wave_dwords * 4)));
+        fused_sp_off[K - kMinK] = total;
+        total += w * fg.sp_wave_dwords;
+    }
+    st = ensure_buffer(&b->counters, &b->counters_bytes, (size_t)(kMaxK - kMinK + 1) * kCounterDwords * 4,
+                       "work counters");
+    if (st != PBVD_OK) return st;
     st = ensure_buffer(&b->sp, &b->sp_bytes, (size_t)std::max<int64_t>(total, 64) * 4, "survivors");
     if (st == PBVD_OK && fault_injected("batch_alloc"))
         st = fail(PBVD_ENOMEM, "injected allocation failure after the survivor area");
@@ -396,6 +490,11 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
         b->per_launch[ci] = per_launch[ci];
         b->sp_off[ci] = sp_off[ci];
     }
+    for (int k = 0; k <= kMaxK - kMinK; ++k) {
+        b->fused[k] = wl.fused[k];
+        b->fused_waves[k] = fused_waves[k];
+        b->fused_sp_off[k] = fused_sp_off[k];
+    }
     b->n_tiles = (int64_t)(wl.heads.size() + wl.descs.size());
     b->n_blocks = wl.n_blocks;
     b->n_stages = wl.n_stages;
@@ -413,32 +512,41 @@ pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out,
     DeviceGuard dg(b->device);
     if (!dg.ok) return fail(PBVD_EHIP, "cannot select device %d", b->device);
     hipStream_t s = (hipStream_t)hip_stream;
-    int active[kMaxCodes], n_active = 0;
+    // launch units: codes with register-kernel tiles (u >= 0: code index)
+    // and persistent launches (u < 0: -1 - (K - kMinK)); there are at most
+    // as many as codes
+    int units[kMaxCodes], n_units = 0;
     for (int ci = 0; ci < b->cs.n; ++ci)
-        if (b->groups[ci].n_tiles > 0) active[n_active++] = ci;
-    if (n_active > 1) {
+        if (b->groups[ci].n_tiles > 0) units[n_units++] = ci;
+    for (int k = 0; k <= kMaxK - kMinK; ++k)
+        if (b->fused[k].n_descs > 0) units[n_units++] = -1 - k;
+    if (n_units == 0) return PBVD_OK;
+    auto launch_unit = [&](int u, hipStream_t st) -> pbvd_status {
+        if (u >= 0)
+            return launch_group(b->cs, u, b->groups[u], (const uint8_t *)d_syms, b->sym_bytes, d_out, b->d_lanes,
+                                b->d_heads, b->d_descs, b->sp + b->sp_off[u], b->per_launch[u], st);
+        const int k = -1 - u;
+        return launch_fused(b->cs, k + kMinK, b->fused[k], (const uint8_t *)d_syms, b->sym_bytes, d_out, b->d_descs,
+                            b->sp + b->fused_sp_off[k], b->fused_waves[k], b->counters + kCounterDwords * k, st);
+    };
+    if (n_units > 1) {
         hipError_t e = hipEventRecord(b->fork, s);
         if (e != hipSuccess) return fail_hip(e, "fork event");
     }
-    // codes after the first on their own streams, the first on the caller's,
+    // units after the first on their own streams, the first on the caller's,
     // then the caller's stream waits for all of them
-    for (int k = 1; k < n_active; ++k) {
-        const int ci = active[k];
-        hipError_t e = hipStreamWaitEvent(b->aux[ci], b->fork, 0);
+    for (int k = 1; k < n_units; ++k) {
+        hipError_t e = hipStreamWaitEvent(b->aux[k], b->fork, 0);
         if (e != hipSuccess) return fail_hip(e, "fork wait");
-        pbvd_status st = launch_group(b->cs, ci, b->groups[ci], (const uint8_t *)d_syms, b->sym_bytes,
-                                      d_out, b->d_lanes, b->d_heads, b->d_descs, b->sp + b->sp_off[ci],
-                                      b->per_launch[ci], b->aux[ci]);
+        pbvd_status st = launch_unit(units[k], b->aux[k]);
         if (st != PBVD_OK) return st;
-        e = hipEventRecord(b->join[ci], b->aux[ci]);
+        e = hipEventRecord(b->join[k], b->aux[k]);
         if (e != hipSuccess) return fail_hip(e, "join event");
     }
-    const int c0 = active[0];
-    pbvd_status st = launch_group(b->cs, c0, b->groups[c0], (const uint8_t *)d_syms, b->sym_bytes, d_out,
-                                  b->d_lanes, b->d_heads, b->d_descs, b->sp + b->sp_off[c0], b->per_launch[c0], s);
+    pbvd_status st = launch_unit(units[0], s);
     if (st != PBVD_OK) return st;
-    for (int k = 1; k < n_active; ++k) {
-        hipError_t e = hipStreamWaitEvent(s, b->join[active[k]], 0);
+    for (int k = 1; k < n_units; ++k) {
+        hipError_t e = hipStreamWaitEvent(s, b->join[k], 0);
         if (e != hipSuccess) return fail_hip(e, "join wait");
     }
     // remember the end of this decode for the next pbvd_batch_set_frames

@@ -31,6 +31,12 @@ using WaveLaunchFn = hipError_t (*)(const pbvd::WaveLaunchRequest &);
 const WaveLaunchFn kWaveLaunchTable[7] = {&pbvd::launch_wave<3>, &pbvd::launch_wave<4>, &pbvd::launch_wave<5>,
                                           &pbvd::launch_wave<6>, &pbvd::launch_wave<7>, &pbvd::launch_wave<8>,
                                           &pbvd::launch_wave<9>};
+using OccupancyFn = int (*)();
+const OccupancyFn kWaveOccupancyTable[7] = {
+    &pbvd::wave_persistent_blocks_per_cu<3>, &pbvd::wave_persistent_blocks_per_cu<4>,
+    &pbvd::wave_persistent_blocks_per_cu<5>, &pbvd::wave_persistent_blocks_per_cu<6>,
+    &pbvd::wave_persistent_blocks_per_cu<7>, &pbvd::wave_persistent_blocks_per_cu<8>,
+    &pbvd::wave_persistent_blocks_per_cu<9>};
 using TileLaunchFn = hipError_t (*)(const pbvd::TileLaunchRequest &);
 #define PBVD_TFN(i, K, R, g0, g1, g2, g3) &pbvd::launch_tiles<i>,
 const TileLaunchFn kTileLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_TFN)};
@@ -120,9 +126,29 @@ int64_t wave_slot_dwords(const pbvd_code &c) {
     return ceil_div(pbvd::wave::pb_dwords(c.K - 1, (int64_t)c.D + 2 * (int64_t)c.L), 64) * 64;
 }
 
+pbvd::wave::WaveCode wave_code(const pbvd_code &c) {
+    pbvd::wave::WaveCode w{};
+    for (int r = 0; r < 4; ++r) w.gen[r] = r < c.R ? c.gen[r] : 0u;
+    w.R = c.R;
+    w.kind = c.input_kind;
+    return w;
+}
+
 hipError_t launch_wave(int K, const pbvd::WaveLaunchRequest &req) {
     if (K < 3 || K > 9) return hipErrorInvalidValue;
     return kWaveLaunchTable[K - 3](req);
+}
+
+int64_t resident_waves(int K) {
+    if (K < 3 || K > 9) return 0;
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    const int per_cu = kWaveOccupancyTable[K - 3]();
+    return (int64_t)cus * per_cu * (pbvd::kBlockThreads / pbvd::kWave);
 }
 
 int max_lb(const pbvd_code &c) {
@@ -467,7 +493,9 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
     }
     if (pb_count == 0) return PBVD_OK;
     const int64_t slot = wave_slot_dwords(c);
-    const int64_t per_launch = launch_limit(p, ws, slot);
+    // single_launch (the debug survivor export): each wave also stores its
+    // per-stage decisions, after the path words of all waves
+    const int64_t per_launch = launch_limit(p, ws, single_launch ? 2 * slot : slot);
     if (per_launch < 1)
         return fail(PBVD_EINVAL, "one PB's survivors (%lld bytes) do not fit the static scratch",
                     (long long)(slot * 4));
@@ -476,7 +504,7 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
                     (long long)per_launch);
     if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
     const int64_t launch_pbs = std::min(pb_count, per_launch);
-    pbvd_status st = ws_survivors(ws, (size_t)(launch_pbs * slot * 4));
+    pbvd_status st = ws_survivors(ws, (size_t)(launch_pbs * slot * 4 * (single_launch ? 2 : 1)));
     if (st != PBVD_OK) return st;
     const int64_t end_bit = std::min(n_bits, (pb_first + pb_count) * D);
     const int64_t out_bits = end_bit - pb_first * D;
@@ -507,9 +535,8 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
     a.terminated = c.terminated;
     a.out_mode = direct ? pbvd::kOutDirect : pbvd::kOutAtomic;
     a.descs = nullptr;
-    for (int r = 0; r < 4; ++r) a.gen[r] = r < c.R ? c.gen[r] : 0u;
-    req.R = c.R;
-    req.input_kind = c.input_kind;
+    a.dec_sp = single_launch ? ws.sp + launch_pbs * slot : nullptr;
+    a.codes[0] = wave_code(c);
     req.stream = stream;
     const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
     for (int64_t w0 = 0; w0 < pb_count; w0 += launch_pbs) {
@@ -749,7 +776,8 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     st = run_decode(p, p->ws, d_syms, n_bits, pb_first, pb_count, d_out_bits, nullptr, s, &g, true, &lb);
     if (st != PBVD_OK || pb_count == 0) return st;
     pbvd::SurvivorView v{};
-    v.sp = p->ws.sp;
+    // the state-parallel kernel's per-stage decisions follow its path words
+    v.sp = lb == kWaveLb ? p->ws.sp + pb_count * wave_slot_dwords(p->code) : p->ws.sp;
     v.wave = lb == kWaveLb ? 1 : 0;
     v.sp_wave_dwords = lb == kWaveLb ? wave_slot_dwords(p->code) : slot_dwords(p->code, lb);
     v.lb = lb;

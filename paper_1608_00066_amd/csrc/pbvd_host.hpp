@@ -46,7 +46,10 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out);
 // at most D + 2L forward stages).
 int64_t wave_slot_dwords(const pbvd_code &c);
 
-// Launches the state-parallel kernel of constraint length req.K.
+// Run-time code description of the state-parallel kernel.
+pbvd::wave::WaveCode wave_code(const pbvd_code &c);
+
+// Launches the state-parallel kernel of constraint length K.
 hipError_t launch_wave(int K, const pbvd::WaveLaunchRequest &req);
 
 // Survivor dwords of one wave slot of a code (all D + 2L forward rows) with
@@ -93,18 +96,33 @@ struct TileGroup {
     int lb = 0;
 };
 
+// The PBs of every state-parallel code of one constraint length, for one
+// persistent launch: descriptors [desc_begin, + n_descs), longest first,
+// each naming its code by its slot in `codes` (flag bits from
+// pbvd::wave::kDescCodeShift).
+struct FusedGroup {
+    int n_codes = 0;
+    int codes[kMaxCodes];           // code set index of each slot
+    int64_t desc_begin = 0, n_descs = 0;
+    int64_t sp_wave_dwords = 0;     // the largest slot of its codes
+};
+constexpr int kMinK = 3, kMaxK = 9;
+
 // Tiles (waves of 64 PBs) of a set of frames, grouped by code.
 struct WorkList {
     std::vector<pbvd::LaneDesc> lanes;   // 64 per tile (register kernel)
     std::vector<pbvd::TileHead> heads;   // one per tile (register kernel)
     std::vector<pbvd::LaneDesc> descs;   // one per PB (state-parallel kernel)
     TileGroup groups[kMaxCodes];
+    FusedGroup fused[kMaxK - kMinK + 1];  // by K (fuse_waves only)
     int64_t n_blocks = 0, n_stages = 0;
 };
 
 // Builds the work list of `frames` (validated against the buffer sizes).
+// fuse_waves: the state-parallel codes of one K share one fused group (and
+// their own groups stay empty); else each code has its own group.
 pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
-                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl);
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves = false);
 
 // Launches the tile kernels of one code group: tiles [g.tile_begin, + g.n_tiles)
 // of the uploaded work list, at most `per_launch` waves per launch sharing
@@ -113,5 +131,17 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
                          int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
                          const pbvd::TileHead *d_heads, const pbvd::LaneDesc *d_descs, uint32_t *sp,
                          int64_t per_launch, hipStream_t stream);
+
+// Launches one persistent state-parallel kernel over fused group g: `waves`
+// waves (survivor area sp, g.sp_wave_dwords each) take its PBs from the
+// work counters at `counter` (pbvd::wave::kCounters of them), which a fill
+// kernel on `stream` zeroes first.
+pbvd_status launch_fused(const CodeSet &cs, int K, const FusedGroup &g, const uint8_t *d_syms,
+                         int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_descs, uint32_t *sp,
+                         int64_t waves, uint32_t *counter, hipStream_t stream);
+
+// Waves of the persistent state-parallel kernel of constraint length K that
+// the device can hold at once (0 on error).
+int64_t resident_waves(int K);
 
 }  // namespace pbvd_host

@@ -76,14 +76,16 @@ hipError_t launch_tiles(const TileLaunchRequest &req);
 // State-parallel kernel (one wave per PB, run-time generators).
 struct WaveLaunchRequest {
     wave::Args args;
-    int R;
-    int input_kind;
-    unsigned grid;       // workgroups of kBlockThreads (4 PBs each)
+    unsigned grid;       // workgroups of kBlockThreads (4 waves each)
     hipStream_t stream;
 };
 // Implemented by the translation unit compiled for constraint length K.
 template <int K>
 hipError_t launch_wave(const WaveLaunchRequest &req);
+// Workgroups of the persistent state-parallel kernel of constraint length K
+// that one compute unit holds at once (0 on error).
+template <int K>
+int wave_persistent_blocks_per_cu();
 
 // Survivor layout of a code: dwords per stored row and stages per row.
 __host__ __device__ constexpr int survivor_row_dwords(int K) { return (1 << (K - 2)) >= 16 ? (1 << (K - 2)) / 16 : 1; }

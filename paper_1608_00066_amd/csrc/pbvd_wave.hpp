@@ -31,17 +31,25 @@
 // symbols (packed in one dword) and the mask.
 //
 // Survivors.  dec = 1 when the lower branch (from S_2j+1) is strictly
-// cheaper, as Eq. 1 with ties to the upper branch; a lane shifts its
-// decision into one dword per slot every stage (v_alignbit), and every W
-// stages (the trip, W = V * floor(32 / V), so a trip starts at phase 0) the
-// dwords go to HBM: [trip][slot][lane], bit W-1-k for the k-th stage of the
-// trip.  The decision stored at position u in stage t belongs to the state
-// rotr_V^((t+1) mod V)(u) after the stage.
+// cheaper, as Eq. 1 with ties to the upper branch.  The survivor memory is
+// kept by register exchange within a trip of W = V * floor(32 / V) stages (a
+// trip starts at phase 0): each position carries the decisions of the
+// survivor path into it, h = h_pred << 1 | dec, its predecessor's word
+// exchanged like the metric.  At the end of a trip the words go to HBM,
+// [trip][slot][lane]: the word at position u holds the W decisions of the
+// survivor into u over the trip, the k-th stage's at bit W-1-k.
 //
-// Traceback (Alg. 1, Kernel 2).  Wave-uniform, on the scalar unit: the
-// traced state is kept as a position P; at stage t its input bit is bit
-// t mod V of P, and the predecessor's position is P with that bit replaced
-// by the stored decision of lane P mod 64 (v_readlane).
+// Traceback (Alg. 1, Kernel 2), a trip at a time on the scalar unit.  A
+// state's input bit is bit t mod V of its position, and the predecessor's
+// position is the position with that bit replaced by the decision; after a
+// whole trip (a multiple of V stages) every bit has been replaced.  So from
+// the position P at a trip's end and its word h (v_readlane of lane P mod
+// 64), the position at the trip's start is the decisions of the trip's
+// first V stages, and the input bits of the trip are the decisions of its
+// stages V.. (for the first W-V stages) followed by the bits of P: two bit
+// reversals and shifts per trip instead of a step per stage.  A debug
+// variant also stores the per-stage decisions of every position, the
+// survivor layout of the plain method.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -137,8 +145,30 @@ struct Job {
     int32_t *pm_out;     // final metrics or null
 };
 
-template <int V, int R, int KIND>
-__device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t *sp_wave) {
+// New metric and path word of a position from its two candidates: the
+// lower (odd) branch wins only when strictly cheaper (Eq. 1, ties to the
+// upper branch); h = (the winner's word) << 1 | dec in one add with carry
+// (h + h + dec).  Written out because the compiler spends three
+// instructions on the word.  A VCC written by a vector instruction is read
+// as a mask two wait states later, and the words written here may be read
+// by DPP (two wait states) right after the statement.
+__device__ __forceinline__ void select_path(int &pm, uint32_t &h, int up, int lo, uint32_t he, uint32_t ho) {
+    asm("v_cmp_lt_i32 vcc, %[lo], %[up]\n\t"
+        "v_min_i32 %[pm], %[lo], %[up]\n\t"
+        "s_nop 0\n\t"
+        "v_cndmask_b32 %[h], %[he], %[ho], vcc\n\t"
+        "v_addc_co_u32 %[h], vcc, %[h], %[h], vcc\n\t"
+        "s_nop 1"
+        : [pm] "=&v"(pm), [h] "=&v"(h)
+        : [lo] "v"(lo), [up] "v"(up), [he] "v"(he), [ho] "v"(ho)
+        : "vcc");
+}
+
+// DEC: also store each stage's decisions (the debug survivor export) at
+// dec_wave, in the [trip][slot][lane] layout of the path words.
+template <int V, bool DEC>
+__device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const WaveCode &code, uint32_t *sp_wave,
+                                          uint32_t *dec_wave) {
     constexpr int N = 1 << V;
     constexpr int SL = slots(V);
     constexpr int NL = N < kWave ? N : kWave;   // distinct positions per slot
@@ -146,8 +176,14 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
     constexpr int W = trip_stages(V);
     constexpr int G = (W + 15) / 16;             // symbol dwords per lane and trip
 
-    const int lane = (int)(threadIdx.x & (kWave - 1));
+    // the lane number through an empty asm statement: what derives from it
+    // (the branch masks above all) is recomputed for each PB instead of
+    // being hoisted out of the persistent loop into registers of their own
+    int lane = (int)(threadIdx.x & (kWave - 1));
+    asm volatile("" : "+v"(lane));
     const int len = j.len;
+    const int R = code.R;
+    const bool hard = code.kind == kHardU8;
     // Trips are aligned to the end of the forward range: trip i holds
     // stages [i*W - off, (i+1)*W - off), so the first trip starts off
     // stages in and the last one ends at stage len, at phase 0.
@@ -168,9 +204,9 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
             const uint32_t reg = (x << V) | se;
             uint32_t mu = 0, ml = 0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                mu |= (uint32_t)parity32(a.gen[r] & reg) << (8 * r);
-                ml |= (uint32_t)parity32(a.gen[r] & (reg | 1u)) << (8 * r);
+            for (int r = 0; r < 4; ++r) {  // generators past R are 0: zero mask bytes
+                mu |= (uint32_t)parity32(code.gen[r] & reg) << (8 * r);
+                ml |= (uint32_t)parity32(code.gen[r] & (reg | 1u)) << (8 * r);
             }
             mup[ph][s] = mu;
             mlo[ph][s] = ml;
@@ -185,6 +221,11 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         const int u = s * kWave + (lane & (NL - 1));
         pm[s] = (j.known && u != 0) ? 8192 : 0;
     }
+
+    // path words (register exchange within a trip)
+    uint32_t hist[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) hist[s] = 0;
 
     uint32_t *const sp_lane = sp_wave + lane;  // [trip][slot][lane]
 
@@ -201,7 +242,7 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         for (int g = 0; g < G; ++g) {
             int t = tt0 + g * 16 + sl;
             t = t < 0 ? 0 : t;  // stages before the first are never used
-            const uint8_t *p = in + (int64_t)t * R;
+            const uint8_t *p = in + (int64_t)t * R;  // R: the code's rate, wave-uniform
             mis[g] = (uint32_t)((uintptr_t)p & 3u);
             const uint8_t *pa = p - mis[g];
             if (pa + 8 <= a.in_end) {
@@ -226,7 +267,7 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             uint32_t q = __builtin_amdgcn_alignbyte(hi[g], lo[g], mis[g]);
-            if constexpr (KIND == kHardU8) q = 0x01010101u + (q & 0x01010101u) * 0xfeu;  // bit -> +1 / -1
+            if (hard) q = 0x01010101u + (q & 0x01010101u) * 0xfeu;  // bit -> +1 / -1
             qv[g] = q;
         }
         // two wait states between these writes and the DPP reads of qv
@@ -236,7 +277,8 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
 
     // one trellis stage, the k-th of its trip (phase k mod V); each
     // candidate is its predecessor's metric plus the branch metric, the dot
-    // product accumulating onto the exchanged metric
+    // product accumulating onto the exchanged metric; the path words follow
+    // the metrics
     auto stage = [&](auto kc, const uint32_t (&qv)[G], uint32_t (&acc)[SL]) PBVD_INLINE_LAMBDA {
         constexpr int k = decltype(kc)::value;
         constexpr int PH = k % V;
@@ -244,11 +286,12 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         if constexpr (PH < LB) {
 #pragma unroll
             for (int s = 0; s < SL; ++s) {
-                int up, lo;
+                int up, lo, he, ho;
                 pair_values<PH>(pm[s], up, lo);
+                pair_values<PH>((int)hist[s], he, ho);
                 dot_pair<k % 16>(up, lo, q, mup[PH][s], mlo[PH][s]);
-                acc[s] = push_sign(acc[s], lo - up);
-                pm[s] = min(up, lo);
+                if constexpr (DEC) acc[s] = push_sign(acc[s], lo - up);
+                select_path(pm[s], hist[s], up, lo, (uint32_t)he, (uint32_t)ho);
             }
         } else {
             constexpr int M = 1 << (PH - 6);  // slot bit
@@ -256,12 +299,15 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
             for (int s = 0; s < SL; ++s) {
                 if (s & M) continue;
                 int up0 = pm[s], lo0 = pm[s | M], up1 = pm[s], lo1 = pm[s | M];
+                const uint32_t he = hist[s], ho = hist[s | M];
                 dot_pair<k % 16>(up0, lo0, q, mup[PH][s], mlo[PH][s]);
                 dot_pair<k % 16>(up1, lo1, q, mup[PH][s | M], mlo[PH][s | M]);
-                acc[s] = push_sign(acc[s], lo0 - up0);
-                acc[s | M] = push_sign(acc[s | M], lo1 - up1);
-                pm[s] = min(up0, lo0);
-                pm[s | M] = min(up1, lo1);
+                if constexpr (DEC) {
+                    acc[s] = push_sign(acc[s], lo0 - up0);
+                    acc[s | M] = push_sign(acc[s | M], lo1 - up1);
+                }
+                select_path(pm[s], hist[s], up0, lo0, he, ho);
+                select_path(pm[s | M], hist[s | M], up1, lo1, he, ho);
             }
         }
     };
@@ -291,7 +337,12 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         }
         // step k of the trip at bit W-1-k
 #pragma unroll
-        for (int s = 0; s < SL; ++s) __builtin_nontemporal_store(acc[s], sp_lane + (trip * SL + s) * kWave);
+        for (int s = 0; s < SL; ++s) __builtin_nontemporal_store(hist[s], sp_lane + (trip * SL + s) * kWave);
+        if constexpr (DEC) {
+#pragma unroll
+            for (int s = 0; s < SL; ++s)
+                __builtin_nontemporal_store(acc[s], dec_wave + lane + (trip * SL + s) * kWave);
+        }
         // exact renormalization: every metric minus one shared value
         const int ref = __builtin_amdgcn_readfirstlane(pm[0]);
 #pragma unroll
@@ -323,14 +374,13 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
     }
 
     // ---- traceback (Alg. 1, Kernel 2) ----
-    // Every step of a trip is traced (the last trip is full; steps below the
-    // decoded range at the bottom are harmless); the input bits of a trip
-    // collect in `word` (bit i = the trip's i-th stage) and the decoded ones
-    // are merged into the output word under assembly after the trip.
+    // A trip at a time from its path word (the last trip is full; stages
+    // below the decoded range at the bottom are harmless); the input bits of
+    // a trip form `word` (bit i = the trip's i-th stage) and the decoded
+    // ones are merged into the output word under assembly.
     const int store0 = j.store0, dec_end = j.dec_end;
     const int n_dec = dec_end - store0;
     const int trip_bot = (store0 + off) / W;
-    uint32_t word = 0;
     int cm = (n_dec - 1) >> 5;  // output word under assembly (relative to the PB)
     uint32_t cw = 0;
 
@@ -358,36 +408,33 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
         }
     };
 
-    // survivor dwords of a trip, loaded a ring of trips ahead
-    constexpr int kRing = 3;
+    // path words of a trip, loaded a ring of trips ahead
+    constexpr int kRing = SL == 1 ? 8 : SL == 2 ? 6 : 4;
     uint32_t ring[kRing][SL];
     auto load_trip = [&](uint32_t (&dst)[SL], int trip) PBVD_INLINE_LAMBDA {
         trip = trip < trip_bot ? trip_bot : trip;
 #pragma unroll
         for (int s = 0; s < SL; ++s) dst[s] = __builtin_nontemporal_load(sp_lane + (trip * SL + s) * kWave);
     };
-    auto run_trip = [&](const uint32_t (&dw)[SL], int trip) PBVD_INLINE_LAMBDA {
-        static_for<0, W>([&](auto ic) PBVD_INLINE_LAMBDA {
-            constexpr int k = W - 1 - decltype(ic)::value;
-            constexpr int ph = k % V;
-            word = (word << 1) | ((P >> ph) & 1u);
-            uint32_t w;
-            if constexpr (SL == 1) {
-                w = (uint32_t)__builtin_amdgcn_readlane((int)dw[0], (int)(P & 63u));
-            } else {
-                const int l = (int)(P & 63u);
-                const uint32_t slot = P >> 6;
-                w = 0;
+    auto run_trip = [&](const uint32_t (&hw)[SL], int trip) PBVD_INLINE_LAMBDA {
+        uint32_t h;
+        if constexpr (SL == 1) {
+            h = (uint32_t)__builtin_amdgcn_readlane((int)hw[0], (int)(P & 63u));
+        } else {
+            const int l = (int)(P & 63u);
+            const uint32_t slot = P >> 6;
+            h = 0;
 #pragma unroll
-                for (int s = 0; s < SL; ++s) {
-                    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)dw[s], l);
-                    w = slot == (uint32_t)s ? v : w;
-                }
+            for (int s = 0; s < SL; ++s) {
+                const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)hw[s], l);
+                h = slot == (uint32_t)s ? v : h;
             }
-            const uint32_t d = (w >> (W - 1 - k)) & 1u;
-            P = (P & ~(1u << ph)) | (d << ph);
-            return true;
-        });
+        }
+        // decision of the trip's stage k: bit W-1-k of h, i.e. bit
+        // 32-W+k of its reversal
+        const uint32_t rev = __builtin_bitreverse32(h);
+        const uint32_t word = (rev >> (32 - W + V)) | (P << (W - V));
+        P = (rev >> (32 - W)) & (uint32_t)(N - 1);
         // decoded stages of the trip: [lo, hi), at bits lo - tt0 .. of word
         const int tt0 = trip * W - off;
         const int lo = store0 > tt0 ? store0 : tt0;
@@ -432,47 +479,93 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, uint32_t 
     flush();  // word 0
 }
 
-// One wave per PB; 4 independent waves per 256-thread workgroup.
+// Job of PB `idx` of a stream (Sec. III-A geometry; stream mode).
+template <int V>
+__device__ __forceinline__ Job stream_job(const Args &a, const uint8_t *syms, int64_t idx) {
+    constexpr int N = 1 << V;
+    Job j;
+    const int64_t b = a.pb_first + idx;
+    const int64_t D = a.D, L = a.L;
+    const int64_t d0 = b * D;
+    const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
+    const int64_t f1 = d0 + D + L > a.T ? a.T : d0 + D + L;
+    const int64_t d1 = d0 + D > a.n ? a.n : d0 + D;
+    j.in = syms + f0 * a.codes[0].R;
+    j.len = (int)(f1 - f0);
+    j.store0 = (int)(d0 - f0);
+    j.dec_end = (int)(d1 - f0);
+    j.known = f0 == 0;
+    j.argmin = f1 == a.T && !a.terminated;
+    j.out_bit0 = idx * D;
+    j.pm_out = a.final_pm ? a.final_pm + idx * N : nullptr;
+    return j;
+}
+
+// Job of descriptor idx of a work list (batches); *code_idx receives its code.
+__device__ __forceinline__ Job desc_job(const Args &a, const uint8_t *syms, int64_t idx, int *code_idx, bool *active) {
+    Job j;
+    const LaneDesc &d = a.descs[idx];
+    j.in = syms + uniform64(d.sym);
+    j.len = __builtin_amdgcn_readfirstlane(d.len);
+    j.store0 = __builtin_amdgcn_readfirstlane(d.store0);
+    j.dec_end = __builtin_amdgcn_readfirstlane(d.dec_end);
+    const int fl = __builtin_amdgcn_readfirstlane(d.flags);
+    j.known = (fl & kLaneKnown) != 0;
+    j.argmin = (fl & kLaneArgmin) != 0;
+    j.out_bit0 = uniform64(d.out_bit);
+    j.pm_out = nullptr;
+    *code_idx = (fl >> kDescCodeShift) & 0xff;
+    *active = (fl & kLaneActive) != 0;
+    return j;
+}
+
+// One wave per PB; 4 independent waves per 256-thread workgroup.  Modes:
+// kModeList, a stream's PBs (descs == null) or a work list's PBs (descs),
+// one per wave; kModePersist, persistent waves that take the work list's
+// PBs in list order (longest first) from work counters until it is exhausted --
+// one launch for the PBs of every code of this K, whatever their count (a
+// kernel of its own: the state it keeps across PBs would cost the other
+// modes a wave per SIMD); kModeDecisions, a stream's PBs with every stage's
+// decisions stored as well (a.dec_sp, the debug survivor export).
 // syms: the symbol buffer (the same pointer as a.syms), a separate parameter
 // so that its loads may use the scalar unit (nothing the kernel writes
 // aliases it).
-template <int V, int R, int KIND>
+template <int V, int MODE>
 __global__ void __launch_bounds__(256) decode_wave_kernel(const Args a, const uint8_t *__restrict__ syms) {
-    constexpr int N = 1 << V;
     const int64_t wl = (int64_t)blockIdx.x * (blockDim.x / kWave) +
                        __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     if (wl >= a.n_waves) return;
-    const int64_t idx = a.wave_begin + wl;
-    Job j;
-    if (a.descs) {
-        const LaneDesc &d = a.descs[idx];
-        j.in = syms + uniform64(d.sym);
-        j.len = __builtin_amdgcn_readfirstlane(d.len);
-        j.store0 = __builtin_amdgcn_readfirstlane(d.store0);
-        j.dec_end = __builtin_amdgcn_readfirstlane(d.dec_end);
-        const int fl = __builtin_amdgcn_readfirstlane(d.flags);
-        j.known = (fl & kLaneKnown) != 0;
-        j.argmin = (fl & kLaneArgmin) != 0;
-        j.out_bit0 = uniform64(d.out_bit);
-        j.pm_out = nullptr;
-        if (!(fl & kLaneActive)) return;
+    uint32_t *const sp = a.sp + wl * a.sp_wave_dwords;
+    if constexpr (MODE == kModePersist) {
+        // The next PB from the counter of this workgroup's XCD (workgroups
+        // go to the 8 XCDs in turn): with nc counters (8, fewer for grids
+        // of fewer workgroups, so that every counter has waves), counter x
+        // hands out PBs x, x + nc, x + 2 nc, ... of the list, so each XCD
+        // takes an equal share of every length, longest first, and the
+        // counters spread the atomics.
+        const int lane = (int)(threadIdx.x & (kWave - 1));
+        const int nc = gridDim.x < (unsigned)kCounters ? (int)gridDim.x : kCounters;
+        const int x = (int)(blockIdx.x % (unsigned)nc);
+        for (;;) {
+            uint32_t got = 0;
+            if (lane == 0) got = atomicAdd(a.counter + kCounterStride * x, 1u);
+            const int64_t idx = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)got) * nc + x;
+            if (idx >= a.n_items) return;
+            int ci;
+            bool active;
+            const Job j = desc_job(a, syms, idx, &ci, &active);
+            if (active) decode_pb<V, false>(a, j, a.codes[ci], sp, nullptr);
+        }
+    } else if constexpr (MODE == kModeDecisions) {
+        decode_pb<V, true>(a, stream_job<V>(a, syms, a.wave_begin + wl), a.codes[0], sp,
+                           a.dec_sp + wl * a.sp_wave_dwords);
     } else {
-        const int64_t b = a.pb_first + idx;
-        const int64_t D = a.D, L = a.L;
-        const int64_t d0 = b * D;
-        const int64_t f0 = d0 - L < 0 ? 0 : d0 - L;
-        const int64_t f1 = d0 + D + L > a.T ? a.T : d0 + D + L;
-        const int64_t d1 = d0 + D > a.n ? a.n : d0 + D;
-        j.in = syms + f0 * R;
-        j.len = (int)(f1 - f0);
-        j.store0 = (int)(d0 - f0);
-        j.dec_end = (int)(d1 - f0);
-        j.known = f0 == 0;
-        j.argmin = f1 == a.T && !a.terminated;
-        j.out_bit0 = idx * D;
-        j.pm_out = a.final_pm ? a.final_pm + idx * N : nullptr;
+        const int64_t idx = a.wave_begin + wl;
+        int ci = 0;
+        bool active = true;
+        const Job j = a.descs ? desc_job(a, syms, idx, &ci, &active) : stream_job<V>(a, syms, idx);
+        if (active) decode_pb<V, false>(a, j, a.codes[ci], sp, nullptr);
     }
-    decode_pb<V, R, KIND>(a, j, a.sp + wl * a.sp_wave_dwords);
 }
 
 }  // namespace wave

@@ -1,5 +1,6 @@
-// State-parallel (one wave per PB) decoder kernels for one constraint length,
-// every rate and input kind.  Compiled once per K with -DPBVD_WAVE_K=<K>.
+// State-parallel (one wave per PB) decoder kernel for one constraint length
+// (every rate and input kind: they are run-time arguments).  Compiled once
+// per K with -DPBVD_WAVE_K=<K>.
 #include "pbvd_wave.hpp"
 #include "pbvd_registry.hpp"
 
@@ -11,26 +12,28 @@ namespace pbvd {
 
 template <int K>
 hipError_t launch_wave(const WaveLaunchRequest &req) {
-    constexpr int V = K - 1;
-    const int R = req.R;
-    const bool hard = req.input_kind == kHardU8;
-#define PBVD_WAVE_CASE(RR)                                                                           \
-    if (R == RR) {                                                                                  \
-        if (hard)                                                                                   \
-            hipLaunchKernelGGL((wave::decode_wave_kernel<V, RR, kHardU8>), dim3(req.grid),          \
-                               dim3(kBlockThreads), 0, req.stream, req.args, req.args.syms);                       \
-        else                                                                                        \
-            hipLaunchKernelGGL((wave::decode_wave_kernel<V, RR, kSoftI8>), dim3(req.grid),          \
-                               dim3(kBlockThreads), 0, req.stream, req.args, req.args.syms);                       \
-        return hipGetLastError();                                                                   \
-    }
-    PBVD_WAVE_CASE(2)
-    PBVD_WAVE_CASE(3)
-    PBVD_WAVE_CASE(4)
-#undef PBVD_WAVE_CASE
-    return hipErrorInvalidValue;
+    if (req.args.counter)
+        hipLaunchKernelGGL((wave::decode_wave_kernel<K - 1, wave::kModePersist>), dim3(req.grid),
+                           dim3(kBlockThreads), 0, req.stream, req.args, req.args.syms);
+    else if (req.args.dec_sp)
+        hipLaunchKernelGGL((wave::decode_wave_kernel<K - 1, wave::kModeDecisions>), dim3(req.grid),
+                           dim3(kBlockThreads), 0, req.stream, req.args, req.args.syms);
+    else
+        hipLaunchKernelGGL((wave::decode_wave_kernel<K - 1, wave::kModeList>), dim3(req.grid),
+                           dim3(kBlockThreads), 0, req.stream, req.args, req.args.syms);
+    return hipGetLastError();
+}
+
+template <int K>
+int wave_persistent_blocks_per_cu() {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, wave::decode_wave_kernel<K - 1, wave::kModePersist>,
+                                                     kBlockThreads, 0) != hipSuccess)
+        return 0;
+    return n;
 }
 
 template hipError_t launch_wave<PBVD_WAVE_K>(const WaveLaunchRequest &req);
+template int wave_persistent_blocks_per_cu<PBVD_WAVE_K>();
 
 }  // namespace pbvd

@@ -1,6 +1,7 @@
-"""Batched decoding (many frames, several codes, one launch per code) against
-the CPU oracle frame by frame, against per-frame stream decoding, and under
-HIP-graph capture and replay."""
+"""Batched decoding (many frames, several codes: one tile launch per
+register-kernel code, one persistent launch per constraint length for the
+state-parallel codes) against the CPU oracle frame by frame, against
+per-frame stream decoding, and under HIP-graph capture and replay."""
 import os
 import sys
 from concurrent.futures import ThreadPoolExecutor
@@ -112,11 +113,13 @@ def test_batch_equal_frames_uniform_tiles(torch, pbvd, lanes):
     check_batch(torch, pbvd, codes, 150, 1000, 1000, seed=31)
 
 
-def test_batch_graph_capture_replays(torch, pbvd):
-    """The decode call only launches kernels: capture it in a HIP graph and
-    replay it several times with eager work in between."""
-    codes = [dict(K=7, gens=(0o171, 0o133), D=512, L=42),
-             dict(K=7, gens=(0o133, 0o171, 0o165), D=512, L=42)]
+@pytest.mark.parametrize("mapping", [0, 2], ids=["auto", "wave"])
+def test_batch_graph_capture_replays(torch, pbvd, mapping):
+    """The decode call only launches kernels (the persistent launch's work
+    counter is reset by a fill kernel): capture it in a HIP graph and replay
+    it several times with eager work in between."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=512, L=42, mapping=mapping),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=512, L=42, mapping=mapping)]
     frames, streams, syms, out_bytes = make_batch(codes, 100, 40, 2000, seed=31, gap=0)
     d_syms = torch.from_numpy(syms).cuda()
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
@@ -249,3 +252,50 @@ def test_batch_codes_outside_the_registry(torch, pbvd):
              dict(K=5, gens=(0o31, 0o6), D=40, L=25, input_kind=1)]      # not registered
     log("batch: registered + unregistered codes, 200 frames")
     check_batch(torch, pbvd, codes, 200, 1, 2500, seed=81)
+
+
+@pytest.mark.parametrize("waves", [1, 5, 64])
+def test_batch_persistent_waves_take_many_blocks(torch, pbvd, monkeypatch, waves):
+    """A persistent launch with few waves: each wave takes many PBs of both
+    K=7 codes (and of the K=9 code in its own launch) from the work counter,
+    longest first; every frame equals the oracle."""
+    monkeypatch.setenv("PBVD_PERSISTENT_WAVES", str(waves))
+    codes = [dict(K=7, gens=(0o171, 0o133), D=64, L=42, mapping=2),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=96, L=42, mapping=2),
+             dict(K=9, gens=(0o557, 0o663, 0o711), D=48, L=54, terminated=False, mapping=2),
+             dict(K=7, gens=(0o171, 0o133), D=128, L=42, terminated=False, input_kind=1, mapping=2)]
+    log("batch persistent, %d waves per launch: 120 frames, lengths 1..2500" % waves)
+    check_batch(torch, pbvd, codes, 120, 1, 2500, seed=91 + waves)
+
+
+def test_batch_persistent_full_size(torch, pbvd):
+    """The full 4096-frame mixed-code workload (K=7 r1/2 and r1/3, lengths
+    40..6144, both codes in one persistent launch): every frame against the
+    oracle, twice in a row (the work counter starts again at zero)."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=128, L=42, mapping=2),
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=128, L=42, mapping=2)]
+    frames, streams, syms, out_bytes = make_batch(codes, 4096, 40, 6144,
+                                                  seed=datagen.config_seed(3, 0, 0), gap=0)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.full((out_bytes,), 0xA5, dtype=torch.uint8, device="cuda")
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+        first = out.clone()
+        out.fill_(0xA5)
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+    assert torch.equal(first, out)
+    host = out.cpu().numpy()
+
+    def frame_ok(f):
+        so, n, oo, ci = frames[f]
+        c = codes[ci]
+        ref = oracle.decode(c["K"], c["gens"], c["D"], c["L"], streams[f]["syms"], n)["bits"]
+        got = np.unpackbits(host[oo:oo + (n + 7) // 8], bitorder="little")[:n]
+        return np.array_equal(got, ref)
+    with ThreadPoolExecutor(max_workers=NTHREADS) as ex:
+        ok = list(ex.map(frame_ok, range(len(frames))))
+    bad = [f for f, v in enumerate(ok) if not v]
+    assert not bad, "%d frames differ from the oracle, first %s" % (len(bad), bad[:8])
