@@ -84,10 +84,18 @@ enum {
  *     state (two or four for K = 8, 9), metrics exchanged between lanes every
  *     stage, generators taken at run time: any code of the ranges below, and
  *     the lowest latency per PB (short streams, single frames).
+ *   PBVD_MAP_GROUP: the paper's group mapping (Sec. III-B Eq. 3-6, Sec. IV-A,
+ *     Alg. 1): the butterflies fall into N_c = 2^R groups by their code word
+ *     alpha; a workgroup of N_c waves decodes 64 PBs, wave w the butterflies
+ *     of group w (four branch metrics per stage), lane l PB l, the metrics
+ *     exchanged through LDS each stage; generators at run time.  Takes codes
+ *     with K - 2 - R >= 0, 2^(K-2-R) <= 16 and groups of one size (the alpha
+ *     map of full rank R; PBVD_ENOTSUP otherwise) and D + 2L <= 2^20;
+ *     lanes_per_pb 0 or 2^R; no survivor export (pbvd_debug_survivors).
  *   PBVD_MAP_AUTO: the wave kernel for codes outside the registry and for
  *     calls with few PBs, the register kernel otherwise.
  * Every mapping gives the same bits and metrics. */
-enum { PBVD_MAP_AUTO = 0, PBVD_MAP_LANES = 1, PBVD_MAP_WAVE = 2 };
+enum { PBVD_MAP_AUTO = 0, PBVD_MAP_LANES = 1, PBVD_MAP_WAVE = 2, PBVD_MAP_GROUP = 3 };
 
 /* Code and block parameters (Sec. III-A, Sec. III-B). */
 typedef struct {
@@ -108,8 +116,9 @@ typedef struct {
                            pm_bits = 16 and K >= 7 (2), K >= 8 (4) or K = 9
                            (8).  More lanes per PB cut a PB's latency and let
                            short streams fill more of the GPU; results are
-                           identical, only the kernel differs */
-    int32_t mapping;    /* PBVD_MAP_AUTO, PBVD_MAP_LANES or PBVD_MAP_WAVE */
+                           identical, only the kernel differs; with
+                           PBVD_MAP_GROUP 0 or 2^R */
+    int32_t mapping;    /* PBVD_MAP_AUTO, PBVD_MAP_LANES, PBVD_MAP_WAVE or PBVD_MAP_GROUP */
 } pbvd_code;
 
 /* Validate `code` (the code of Eq. 2 and the blocks of Sec. III-A) and pick
@@ -193,7 +202,8 @@ pbvd_status pbvd_decode_ex_noalloc(pbvd_plan *p, const void *d_syms, int64_t n_b
 pbvd_status pbvd_decode_host(pbvd_plan *p, const void *h_syms, int64_t n_bits, uint8_t *h_out,
                              int32_t n_streams, int64_t chunk_pbs, uint32_t flags);
 
-/* Lanes per PB (1, 2, 4, 8, or 64 for the wave mapping) that pbvd_decode_ex
+/* Lanes per PB (1, 2, 4, 8, 64 for the wave mapping, 2^R for the group
+ * mapping) that pbvd_decode_ex
  * of PBs [pb_first, pb_first + pb_count) of an n_bits-bit stream uses: the
  * plan's mapping and lanes_per_pb, or the library's choice: the wave
  * mapping for codes outside the registry and for calls of fewer PBs than a
@@ -232,6 +242,17 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
  * per-stage constant shared by all code words.  Asynchronous. */
 pbvd_status pbvd_debug_branch_metrics(pbvd_plan *p, const void *d_syms, int64_t n_stages,
                                       int32_t *d_bm, void *hip_stream);
+
+/* Verification hook for the group mapping (host only, no device work): the
+ * classification of Sec. III-B (Eq. 3-6, Table II) the library derives from
+ * `code`'s generators.  alpha[j] (N/2 entries) receives the group of
+ * butterfly j, its code word alpha = c(S_2j, 0) with c^(1) as the most
+ * significant bit; masks[4 * a + t] (2^R x 4 entries) the code words of
+ * group a's four branches, t = 0..3 for alpha, beta = c(S_2j, 1),
+ * gamma = c(S_2j+1, 0), theta = c(S_2j+1, 1), in the same bit order.  Both
+ * arrays are caller-owned host memory.  PBVD_ENOTSUP when the mapping does
+ * not take the code (see PBVD_MAP_GROUP), PBVD_EINVAL for an invalid code. */
+pbvd_status pbvd_debug_group_table(const pbvd_code *code, int32_t *alpha, int32_t *masks);
 
 /* Free the plan and its device workspace (synchronizes the device). */
 void pbvd_destroy(pbvd_plan *p);
@@ -328,7 +349,7 @@ typedef struct {
 /* Create a server for n_codes (1..16) code/block parameter sets (each valid
  * for pbvd_batch_create) on the current device.  Codes that leave the mapping
  * to the library (PBVD_MAP_AUTO, lanes_per_pb 0) decode on the wave mapping,
- * the lowest latency per request.  Allocates the device budget and pinned
+ * the lowest latency per request; PBVD_ENOTSUP for PBVD_MAP_GROUP.  Allocates the device budget and pinned
  * staging buffers and starts the worker thread (which polls for 2 ms after
  * its last work before it sleeps, to admit requests quickly). */
 pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pbvd_server_config *cfg,

@@ -59,6 +59,8 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
     for k in range(3, 10):
         units.append((os.path.join(csrc, "pbvd_wave_inst.hip"),
                       os.path.join(build_dir, "wave_k%d.o" % k), ["-DPBVD_WAVE_K=%d" % k]))
+        units.append((os.path.join(csrc, "pbvd_group_inst.hip"),
+                      os.path.join(build_dir, "group_k%d.o" % k), ["-DPBVD_GROUP_K=%d" % k]))
     for name in ("pbvd_capi", "pbvd_batch", "pbvd_server", "pbvd_aux"):
         units.append((os.path.join(csrc, name + ".hip"), os.path.join(build_dir, name + ".o"), []))
 

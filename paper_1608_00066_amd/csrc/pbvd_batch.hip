@@ -36,8 +36,10 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
         cs.idx[i] = idx;
         const int req = requested_lb(codes[i]);
         const int top = max_lb(codes[i]);
-        cs.lb[i] = idx < 0 || (req < 0 && auto_lb == kWaveLb) ? kWaveLb
+        cs.lb[i] = req == kGroupLb ? kGroupLb
+                   : idx < 0 || (req < 0 && auto_lb == kWaveLb) ? kWaveLb
                    : req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
+        if (cs.lb[i] == kGroupLb) (void)group_tables(cs.codes[i], &cs.gtab[i]);  // checked by check_code
     }
     cs.n = n;
     *out = cs;
@@ -135,6 +137,25 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
         const int64_t U = pbvd::trip_stages(c.K);
         const int64_t ND = pbvd::trip_fetch_dwords(c.K, c.R);
         const int lb = cs.lb[ci];
+        if (lb == kGroupLb) {
+            // tiles of 64 PBs, longest first (a tile runs as long as its
+            // longest PB); the last tile padded with inactive descriptors
+            std::vector<PbRec> &v = per_code[ci];
+            std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) { return x.len > y.len; });
+            const int64_t tp = pbvd::group::kTilePbs;
+            const int64_t nt = ceil_div((int64_t)v.size(), tp);
+            wl->groups[ci].tile_begin = (int64_t)wl->descs.size();
+            for (int64_t k = 0; k < nt * tp; ++k) {
+                const PbRec &r = v[k < (int64_t)v.size() ? k : 0];
+                pbvd::LaneDesc d{r.sym, r.out_bit, r.len, r.store0, r.dec_end, r.flags};
+                if (k >= (int64_t)v.size()) d.flags &= ~pbvd::kLaneActive;
+                wl->descs.push_back(d);
+            }
+            wl->groups[ci].n_tiles = nt;
+            wl->groups[ci].sp_wave_dwords = group_tile_dwords(c);
+            wl->groups[ci].lb = lb;
+            continue;
+        }
         if (lb == kWaveLb) {
             // one wave per PB, longest first (fused: already listed, empty here)
             std::vector<PbRec> &v = per_code[ci];
@@ -213,6 +234,31 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
                          int64_t sym_bytes, uint8_t *d_out, const pbvd::LaneDesc *d_lanes,
                          const pbvd::TileHead *d_heads, const pbvd::LaneDesc *d_descs, uint32_t *sp,
                          int64_t per_launch, hipStream_t stream) {
+    if (g.lb == kGroupLb) {
+        const pbvd_code &c = cs.codes[ci];
+        pbvd::GroupLaunchRequest req{};
+        pbvd::group::GroupArgs &a = req.args;
+        a = cs.gtab[ci];
+        a.syms = d_syms;
+        a.in_end = d_syms + sym_bytes;
+        a.out = d_out;
+        a.out_mode = pbvd::kOutBytes;
+        a.kind = c.input_kind;
+        a.final_pm = nullptr;
+        a.sp = sp;
+        a.sp_tile_dwords = g.sp_wave_dwords;
+        a.descs = d_descs + g.tile_begin;
+        req.R = c.R;
+        req.stream = stream;
+        for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
+            a.tile_begin = t0;
+            a.n_tiles = std::min(per_launch, g.n_tiles - t0);
+            req.grid = (unsigned)a.n_tiles;
+            hipError_t e = launch_group_kernel(c.K, req);
+            if (e != hipSuccess) return fail_hip(e, "batch group kernel launch");
+        }
+        return PBVD_OK;
+    }
     if (g.lb == kWaveLb) {
         const pbvd_code &c = cs.codes[ci];
         pbvd::WaveLaunchRequest req{};

@@ -37,6 +37,11 @@ const OccupancyFn kWaveOccupancyTable[7] = {
     &pbvd::wave_persistent_blocks_per_cu<5>, &pbvd::wave_persistent_blocks_per_cu<6>,
     &pbvd::wave_persistent_blocks_per_cu<7>, &pbvd::wave_persistent_blocks_per_cu<8>,
     &pbvd::wave_persistent_blocks_per_cu<9>};
+using GroupLaunchFn = hipError_t (*)(const pbvd::GroupLaunchRequest &);
+const GroupLaunchFn kGroupLaunchTable[7] = {
+    &pbvd::launch_group_kernel<3>, &pbvd::launch_group_kernel<4>, &pbvd::launch_group_kernel<5>,
+    &pbvd::launch_group_kernel<6>, &pbvd::launch_group_kernel<7>, &pbvd::launch_group_kernel<8>,
+    &pbvd::launch_group_kernel<9>};
 using TileLaunchFn = hipError_t (*)(const pbvd::TileLaunchRequest &);
 #define PBVD_TFN(i, K, R, g0, g1, g2, g3) &pbvd::launch_tiles<i>,
 const TileLaunchFn kTileLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_TFN)};
@@ -118,12 +123,56 @@ int64_t slot_dwords(const pbvd_code &c, int lb) {
 }
 
 int requested_lb(const pbvd_code &c) {
+    if (c.mapping == PBVD_MAP_GROUP) return kGroupLb;
     if (c.mapping == PBVD_MAP_WAVE || c.lanes_per_pb == 64) return kWaveLb;
     return c.lanes_per_pb == 8 ? 3 : c.lanes_per_pb == 4 ? 2 : c.lanes_per_pb == 2 ? 1 : c.lanes_per_pb == 1 ? 0 : -1;
 }
 
 int64_t wave_slot_dwords(const pbvd_code &c) {
     return ceil_div(pbvd::wave::pb_dwords(c.K - 1, (int64_t)c.D + 2 * (int64_t)c.L), 64) * 64;
+}
+
+bool group_tables(const pbvd_code &c, pbvd::group::GroupArgs *a) {
+    if (!pbvd::group::shape_ok(c.K, c.R)) return false;
+    const int V = c.K - 1, N = 1 << V, HALF = N / 2, NC = 1 << c.R, B = HALF / NC, WB = 2 * B;
+    // code word c(d, x) of Eq. 2 as R bits (bit r = c^(r+1))
+    auto word = [&](int d, int x) {
+        const uint32_t reg = ((uint32_t)x << V) | (uint32_t)d;
+        int cw = 0;
+        for (int r = 0; r < c.R; ++r) cw |= (__builtin_popcount(c.gen[r] & reg) & 1) << r;
+        return cw;
+    };
+    auto mask = [&](int cw) {
+        uint32_t m = 0;
+        for (int r = 0; r < c.R; ++r) m |= (uint32_t)((cw >> r) & 1) << (8 * r);
+        return m;
+    };
+    int count[16] = {};
+    for (int j = 0; j < HALF; ++j) {
+        const int w = word(2 * j, 0);  // alpha, the group
+        if (count[w] == B) return false;
+        // beta, gamma, theta of the group follow from alpha (Eq. 4-6)
+        const uint32_t m[4] = {mask(w), mask(word(2 * j, 1)), mask(word(2 * j + 1, 0)), mask(word(2 * j + 1, 1))};
+        if (count[w] == 0) {
+            for (int t = 0; t < 4; ++t) a->bm_mask[w][t] = m[t];
+        } else {
+            for (int t = 0; t < 4; ++t)
+                if (a->bm_mask[w][t] != m[t]) return false;
+        }
+        const int b = count[w]++;
+        a->jtab[w * B + b] = (uint8_t)j;
+        // decision of S_j (pushed first) and S_j+N/2 of butterfly b: the
+        // stage's field of group w, first pushed at its top bit
+        a->ttab[j] = (uint8_t)(w * WB + 2 * b);
+        a->ttab[j + HALF] = (uint8_t)(w * WB + 2 * b + 1);
+    }
+    for (int w = 0; w < NC; ++w)
+        if (count[w] != B) return false;
+    return true;
+}
+
+int64_t group_tile_dwords(const pbvd_code &c) {
+    return pbvd::group::tile_dwords(c.K, c.R, (int64_t)c.D + 2 * (int64_t)c.L);
 }
 
 pbvd::wave::WaveCode wave_code(const pbvd_code &c) {
@@ -137,6 +186,11 @@ pbvd::wave::WaveCode wave_code(const pbvd_code &c) {
 hipError_t launch_wave(int K, const pbvd::WaveLaunchRequest &req) {
     if (K < 3 || K > 9) return hipErrorInvalidValue;
     return kWaveLaunchTable[K - 3](req);
+}
+
+hipError_t launch_group_kernel(int K, const pbvd::GroupLaunchRequest &req) {
+    if (K < 3 || K > 9) return hipErrorInvalidValue;
+    return kGroupLaunchTable[K - 3](req);
 }
 
 int64_t resident_waves(int K) {
@@ -184,9 +238,26 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
     if (c.input_kind != PBVD_SOFT_I8 && c.input_kind != PBVD_HARD_U8)
         return fail(PBVD_EINVAL, "input_kind must be PBVD_SOFT_I8 or PBVD_HARD_U8");
     if (c.pm_bits != 16 && c.pm_bits != 32) return fail(PBVD_EINVAL, "pm_bits must be 16 or 32");
-    if (c.mapping != PBVD_MAP_AUTO && c.mapping != PBVD_MAP_LANES && c.mapping != PBVD_MAP_WAVE)
-        return fail(PBVD_EINVAL, "mapping must be PBVD_MAP_AUTO, PBVD_MAP_LANES or PBVD_MAP_WAVE (got %d)",
+    if (c.mapping != PBVD_MAP_AUTO && c.mapping != PBVD_MAP_LANES && c.mapping != PBVD_MAP_WAVE &&
+        c.mapping != PBVD_MAP_GROUP)
+        return fail(PBVD_EINVAL,
+                    "mapping must be PBVD_MAP_AUTO, PBVD_MAP_LANES, PBVD_MAP_WAVE or PBVD_MAP_GROUP (got %d)",
                     c.mapping);
+    if (c.mapping == PBVD_MAP_GROUP) {
+        if (c.lanes_per_pb != 0 && c.lanes_per_pb != (1 << c.R))
+            return fail(PBVD_EINVAL, "the group mapping uses 2^R = %d lanes per PB (lanes_per_pb %d)", 1 << c.R,
+                        c.lanes_per_pb);
+        pbvd::group::GroupArgs t{};
+        if (!group_tables(c, &t))
+            return fail(PBVD_ENOTSUP,
+                        "the group mapping needs K - 2 - R >= 0, at most 32 decisions per group and stage, "
+                        "and 2^R butterfly groups of one size (K=%d R=%d)",
+                        c.K, c.R);
+        if ((int64_t)c.D + 2 * (int64_t)c.L > (1 << 20))
+            return fail(PBVD_ENOTSUP, "the group mapping's 32-bit metrics take D + 2L <= 2^20");
+        *idx_out = -1;
+        return PBVD_OK;
+    }
     if (c.lanes_per_pb != 0 && c.lanes_per_pb != 1 && c.lanes_per_pb != 2 && c.lanes_per_pb != 4 &&
         c.lanes_per_pb != 8 && c.lanes_per_pb != 64)
         return fail(PBVD_EINVAL, "lanes_per_pb must be 0, 1, 2, 4, 8 or 64 (got %d)", c.lanes_per_pb);
@@ -426,6 +497,7 @@ struct pbvd_plan {
     pbvd_code code;
     int code_idx;             // register kernel's registry index, -1: none
     int64_t wave_max_pbs;     // auto mapping: the wave kernel up to this many PBs
+    pbvd::group::GroupArgs gt;  // group mapping: the code's tables
     int device;
     int ndw;                  // survivor dwords per stored row
     int row_stages;           // stages per stored row
@@ -553,6 +625,81 @@ pbvd_status run_decode_wave(pbvd_plan *p, Workspace &ws, const void *d_syms, int
     return PBVD_OK;
 }
 
+// The group-mapped kernel for one call: tiles of 64 consecutive PBs, in
+// launches of as many tiles as the survivor workspace holds.
+pbvd_status run_decode_group(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
+                             int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
+                             hipStream_t stream, CallGeometry *geo_out, bool single_launch) {
+    const pbvd_code &c = p->code;
+    const int64_t D = c.D;
+    const int64_t T = n_bits + (c.terminated ? c.K - 1 : 0);
+    const int64_t tiles = ceil_div(pb_count, pbvd::group::kTilePbs);
+    if (geo_out) {
+        *geo_out = CallGeometry{};
+        geo_out->T = T;
+        geo_out->pb_first = pb_first;
+        geo_out->pb_end = pb_first + pb_count;
+        geo_out->n_waves = tiles << c.R;
+    }
+    if (pb_count == 0) return PBVD_OK;
+    if (single_launch) return fail(PBVD_ENOTSUP, "the group mapping has no survivor export");
+    const int64_t slot = group_tile_dwords(c);
+    const int64_t per_launch = launch_limit(p, ws, slot);
+    if (per_launch < 1)
+        return fail(PBVD_EINVAL, "one tile's survivors (%lld bytes) do not fit the static scratch",
+                    (long long)(slot * 4));
+    if (fault_injected("launch")) return fail(PBVD_EHIP, "injected launch failure");
+    const int64_t launch_tiles = std::min(tiles, per_launch);
+    pbvd_status st = ws_survivors(ws, (size_t)(launch_tiles * slot * 4));
+    if (st != PBVD_OK) return st;
+    const int64_t end_bit = std::min(n_bits, (pb_first + pb_count) * D);
+    const int64_t out_bits = end_bit - pb_first * D;
+    const int64_t out_bytes = ceil_div(out_bits, 8);
+    const bool direct = (D % 32 == 0) && (((uintptr_t)d_out & 3u) == 0);
+    if (!direct) {
+        const int64_t nwords = ceil_div(out_bits, 32) + 2;
+        st = ws_staging(ws, (size_t)nwords * 4);
+        if (st != PBVD_OK) return st;
+        hipError_t e = pbvd::fill_u32(ws.words, nwords, 0u, stream);
+        if (e != hipSuccess) return fail_hip(e, "zero-fill launch");
+    }
+    pbvd::GroupLaunchRequest req{};
+    pbvd::group::GroupArgs &a = req.args;
+    a = p->gt;
+    a.syms = (const uint8_t *)d_syms;
+    a.in_end = a.syms + T * c.R;
+    a.out = d_out;
+    a.out_words = direct ? nullptr : ws.words;
+    a.out_bytes = out_bytes;
+    a.out_mode = direct ? pbvd::kOutDirect : pbvd::kOutAtomic;
+    a.kind = c.input_kind;
+    a.final_pm = d_final_pm;
+    a.sp = ws.sp;
+    a.sp_tile_dwords = slot;
+    a.n = n_bits;
+    a.T = T;
+    a.pb_first = pb_first;
+    a.pb_count = pb_count;
+    a.D = c.D;
+    a.L = c.L;
+    a.terminated = c.terminated;
+    a.descs = nullptr;
+    req.R = c.R;
+    req.stream = stream;
+    for (int64_t t0 = 0; t0 < tiles; t0 += launch_tiles) {
+        a.tile_begin = t0;
+        a.n_tiles = std::min(launch_tiles, tiles - t0);
+        req.grid = (unsigned)a.n_tiles;
+        hipError_t e = launch_group_kernel(c.K, req);
+        if (e != hipSuccess) return fail_hip(e, "group decode kernel launch");
+    }
+    if (!direct) {
+        hipError_t e = pbvd::words_to_bytes(ws.words, d_out, out_bytes, stream);
+        if (e != hipSuccess) return fail_hip(e, "output copy launch");
+    }
+    return PBVD_OK;
+}
+
 // Runs the decode kernels of one call; fills *geo with the decomposition.
 pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t n_bits,
                        int64_t pb_first, int64_t pb_count, uint8_t *d_out, int32_t *d_final_pm,
@@ -564,6 +711,11 @@ pbvd_status run_decode(pbvd_plan *p, Workspace &ws, const void *d_syms, int64_t 
         if (lb_out) *lb_out = lb;
         return run_decode_wave(p, ws, d_syms, n_bits, pb_first, pb_count, d_out, d_final_pm, stream,
                                geo_out, single_launch);
+    }
+    if (lb == kGroupLb) {
+        if (lb_out) *lb_out = lb;
+        return run_decode_group(p, ws, d_syms, n_bits, pb_first, pb_count, d_out, d_final_pm, stream,
+                                geo_out, single_launch);
     }
     const int64_t sp_wave_dwords = slot_dwords(c, lb);
     const CallGeometry g = call_geometry(c, n_bits, pb_first, pb_count, lb, d_final_pm ? 0 : p->n_simd);
@@ -650,6 +802,7 @@ pbvd_status pbvd_create(const pbvd_code *code, pbvd_plan **out) {
     p->code = c;
     for (int r = c.R; r < 4; ++r) p->code.gen[r] = 0;
     p->code_idx = idx;
+    if (c.mapping == PBVD_MAP_GROUP) (void)group_tables(p->code, &p->gt);  // checked by check_code
     if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
     (void)hipGetLastError();
     p->ndw = pbvd::survivor_row_dwords(c.K);
@@ -731,7 +884,8 @@ pbvd_status pbvd_decode(pbvd_plan *p, const void *d_syms, int64_t n_bits, uint8_
 
 int32_t pbvd_call_lanes(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
     if (!p || n_bits < 1 || pb_first < 0 || pb_count < 0) return 0;
-    return 1 << call_lb(p, n_bits, pb_first, pb_count);
+    const int lb = call_lb(p, n_bits, pb_first, pb_count);
+    return lb == kGroupLb ? 1 << p->code.R : 1 << lb;
 }
 
 int64_t pbvd_num_blocks(const pbvd_plan *p, int64_t n_bits) {
@@ -797,6 +951,31 @@ pbvd_status pbvd_debug_survivors(pbvd_plan *p, const void *d_syms, int64_t n_bit
     if (e != hipSuccess) return fail_hip(e, "survivor expansion launch");
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail_hip(e, "hipStreamSynchronize");
+    return PBVD_OK;
+}
+
+pbvd_status pbvd_debug_group_table(const pbvd_code *code, int32_t *alpha, int32_t *masks) {
+    g_last_error[0] = 0;
+    if (!code || !alpha || !masks) return fail(PBVD_EINVAL, "NULL argument");
+    pbvd_code c = *code;
+    c.mapping = PBVD_MAP_GROUP;
+    c.lanes_per_pb = 0;
+    int idx = -1;
+    const pbvd_status st = check_code(c, &idx);
+    if (st != PBVD_OK) return st;
+    pbvd::group::GroupArgs t{};
+    if (!group_tables(c, &t)) return fail(PBVD_ENOTSUP, "no group table for this code");
+    const int HALF = 1 << (c.K - 2), NC = 1 << c.R, B = HALF / NC;
+    // table bit r (byte r of a mask) is c^(r+1); the export puts c^(1) first
+    auto word = [&](uint32_t m) {
+        int32_t v = 0;
+        for (int r = 0; r < c.R; ++r) v |= (int32_t)((m >> (8 * r)) & 1u) << (c.R - 1 - r);
+        return v;
+    };
+    for (int w = 0; w < NC; ++w) {
+        for (int b = 0; b < B; ++b) alpha[t.jtab[w * B + b]] = word(t.bm_mask[w][0]);
+        for (int k = 0; k < 4; ++k) masks[4 * word(t.bm_mask[w][0]) + k] = word(t.bm_mask[w][k]);
+    }
     return PBVD_OK;
 }
 

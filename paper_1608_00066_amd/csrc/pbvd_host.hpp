@@ -37,6 +37,22 @@ pbvd_status ensure_buffer(uint32_t **buf, size_t *have, size_t need, const char 
 
 // log2 of the lanes per PB of the state-parallel kernel (a whole wave).
 constexpr int kWaveLb = 6;
+// Marks the group mapping (2^R lanes per PB, one wave per butterfly group)
+// where a lane-group width is expected.
+constexpr int kGroupLb = 7;
+
+// The group mapping's tables of a code (Sec. III-B): branch-metric masks,
+// the butterflies of each group and the traceback positions; false when the
+// code's groups are not all of one size (alpha map below full rank) or the
+// shape is outside the mapping.
+bool group_tables(const pbvd_code &c, pbvd::group::GroupArgs *a);
+
+// Survivor dwords of one tile (64 PBs of at most D + 2L stages) of the
+// group mapping.
+int64_t group_tile_dwords(const pbvd_code &c);
+
+// Launches the group-mapped kernel of constraint length K.
+hipError_t launch_group_kernel(int K, const pbvd::GroupLaunchRequest &req);
 
 // Validates a code/block parameter set; *idx_out receives its registry index
 // (-1: no register kernel; the wave mapping decodes it).
@@ -76,7 +92,8 @@ struct CodeSet {
     int n = 0;
     pbvd_code codes[kMaxCodes];
     int idx[kMaxCodes];
-    int lb[kMaxCodes];   // lanes per PB used for each code (log2)
+    int lb[kMaxCodes];   // lanes per PB used for each code (log2; kWaveLb, kGroupLb)
+    pbvd::group::GroupArgs gtab[kMaxCodes];  // tables of the group-mapped codes
 };
 
 // Validates n codes for batched use (D % 8 == 0) into *out.  Codes that let
@@ -89,7 +106,9 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
 // The work of one code: tiles of the register kernel (waves of 64 >> lb
 // PBs; tile_begin indexes the heads, 64 lane descriptors per tile), or, with
 // lb == kWaveLb, PBs of the state-parallel kernel (one wave each;
-// tile_begin indexes the PB descriptors).
+// tile_begin indexes the PB descriptors), or, with lb == kGroupLb, tiles of
+// 64 PBs of the group-mapped kernel (tile_begin indexes the PB descriptors,
+// 64 per tile; sp_wave_dwords is per tile).
 struct TileGroup {
     int64_t tile_begin = 0, n_tiles = 0;
     int64_t sp_wave_dwords = 0;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pbvd_group_args.hpp"
 #include "pbvd_kernel.hpp"
 #include "pbvd_wave_args.hpp"
 
@@ -82,6 +83,17 @@ struct WaveLaunchRequest {
 // Implemented by the translation unit compiled for constraint length K.
 template <int K>
 hipError_t launch_wave(const WaveLaunchRequest &req);
+// Group-mapped kernel (a workgroup of 2^R waves per tile of 64 PBs).
+struct GroupLaunchRequest {
+    group::GroupArgs args;
+    int R;
+    unsigned grid;       // tiles of this launch
+    hipStream_t stream;
+};
+// Implemented by the translation unit compiled for constraint length K.
+template <int K>
+hipError_t launch_group_kernel(const GroupLaunchRequest &req);
+
 // Workgroups of the persistent state-parallel kernel of constraint length K
 // that one compute unit holds at once (0 on error).
 template <int K>

@@ -416,6 +416,10 @@ pbvd_status pbvd_server_create(const pbvd_code *codes, int32_t n_codes, const pb
     // the state-parallel kernel (a PB 64 lanes wide)
     pbvd_status st = make_code_set(codes, n_codes, &cs, kWaveLb);
     if (st != PBVD_OK) return st;
+    for (int ci = 0; ci < cs.n; ++ci)
+        if (cs.lb[ci] == kGroupLb)
+            return fail(PBVD_ENOTSUP, "code %d: the server decodes on the register or the state-parallel mapping",
+                        ci);
     pbvd_server *sv = new (std::nothrow) pbvd_server();
     if (!sv) return fail(PBVD_ENOMEM, "host allocation failed");
     sv->cs = cs;

@@ -28,6 +28,7 @@ PBVD_HOST_PINNED = 1
 PBVD_MAP_AUTO = 0
 PBVD_MAP_LANES = 1
 PBVD_MAP_WAVE = 2
+PBVD_MAP_GROUP = 3
 
 
 class pbvd_code(ctypes.Structure):
@@ -76,6 +77,7 @@ SIGNATURES = {
     "pbvd_block_geometry": (_I32, [_P, _I64, _I64, _I64, _P]),
     "pbvd_debug_survivors": (_I32, [_P, _P, _I64, _I64, _I64, _P, _P, _P]),
     "pbvd_debug_branch_metrics": (_I32, [_P, _P, _I64, _P, _P]),
+    "pbvd_debug_group_table": (_I32, [ctypes.POINTER(pbvd_code), _P, _P]),
     "pbvd_destroy": (None, [_P]),
     "pbvd_batch_create": (_I32, [_P, _I32, ctypes.POINTER(_P)]),
     "pbvd_batch_set_frames": (_I32, [_P, _P, _I64, _I64, _I64]),
@@ -321,6 +323,19 @@ def _code_struct(K, gens, D, L, terminated=True, input_kind=PBVD_SOFT_I8, pm_bit
     c.lanes_per_pb = lanes_per_pb
     c.mapping = mapping
     return c
+
+
+def group_table(K, gens):
+    """pbvd_debug_group_table: (alpha of each butterfly [N/2], code words of
+    each group's alpha, beta, gamma, theta [2^R][4]) as numpy arrays, c^(1)
+    the most significant bit."""
+    import numpy as np
+    c = _code_struct(K, gens, 64, 0, mapping=PBVD_MAP_GROUP)
+    alpha = np.zeros(1 << (K - 2), dtype=np.int32)
+    masks = np.zeros((1 << len(gens), 4), dtype=np.int32)
+    _check(lib().pbvd_debug_group_table(ctypes.byref(c), alpha.ctypes.data, masks.ctypes.data),
+           "pbvd_debug_group_table")
+    return alpha, masks
 
 
 class Batch:

@@ -50,7 +50,11 @@ def test_strerror(pbvd):
     (dict(gens=(0o171, 0o1133)), -1), (dict(gens=(0o71, 0o33)), -1), (dict(gens=(0o171, 0)), -1),
     (dict(D=0), -1), (dict(L=-1), -1), (dict(D=1 << 29, L=1 << 28), -1),
     (dict(input_kind=2), -1), (dict(pm_bits=8), -1), (dict(terminated=2), -1),
-    (dict(mapping=3), -1), (dict(lanes_per_pb=3), -1), (dict(lanes_per_pb=16), -1),
+    (dict(mapping=4), -1), (dict(lanes_per_pb=3), -1), (dict(lanes_per_pb=16), -1),
+    # the group mapping: 2^R lanes, K - 2 - R >= 0, at most 32 decisions per
+    # group and stage, groups of one size
+    (dict(mapping=3, lanes_per_pb=2), -1), (dict(K=3, gens=(0o7, 0o5), mapping=3), -2),
+    (dict(K=9, gens=(0o561, 0o753), mapping=3), -2), (dict(K=5, gens=(0o21, 0o31), mapping=3), -2),
     (dict(mapping=2, lanes_per_pb=2), -1), (dict(mapping=1, lanes_per_pb=64), -1),
     # the register kernel exists for the registry's generator sets only
     (dict(gens=(0o171, 0o135), mapping=1), -2), (dict(gens=(0o171, 0o135), lanes_per_pb=2), -2),
@@ -226,4 +230,65 @@ def test_call_lanes_choice(pbvd):
     assert ei.value.status == pbvd.PBVD_EINVAL
     with pytest.raises(pbvd.PbvdError) as ei:
         pbvd.Plan(8, (0o247, 0o371), 512, 48, lanes_per_pb=8)
+    assert ei.value.status == pbvd.PBVD_ENOTSUP
+
+
+def test_group_table_is_table2(pbvd):
+    """The group mapping's classification of the (171,133) code is the
+    paper's Table II: each butterfly's alpha and each group's alpha, beta,
+    gamma, theta (Sec. III-B)."""
+    alpha, masks = pbvd.group_table(7, (0o171, 0o133))
+    seen = set()
+    with open(os.path.join(ROOT, "tests", "golden", "table2_k7_171_133.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            head, states = line.split(":")
+            _, a, b, g, t = head.split()
+            want = [int(x, 2) for x in (a, b, g, t)]
+            assert masks[want[0]].tolist() == want
+            for d in map(int, states.split()):
+                assert alpha[d // 2] == want[0], d
+                seen.add(d // 2)
+    assert seen == set(range(32))
+
+
+GROUP_CODES = [(7, (0o171, 0o133)), (7, (0o133, 0o171, 0o165)), (9, (0o557, 0o663, 0o711)),
+               (5, (0o23, 0o35)), (6, (0o53, 0o75)), (8, (0o247, 0o371)), (6, (0o47, 0o53, 0o75)),
+               (7, (0o117, 0o127, 0o155, 0o171)), (8, (0o237, 0o350, 0o222)), (4, (0o13, 0o17))]
+
+
+@pytest.mark.parametrize("K,gens", GROUP_CODES)
+def test_group_table_follows_eq3_to_eq6(pbvd, K, gens):
+    """For codes the group mapping takes: butterfly j's group is the oracle's
+    label of (S_2j, 0), every group's other words follow Eq. 4-6 from alpha
+    (beta = alpha ^ g_{K-1}, gamma = alpha ^ g_0, theta = both), and all 2^R
+    groups hold 2^(K-2-R) butterflies."""
+    R = len(gens)
+    nxt, lab = oracle.trellis(K, gens)
+    alpha, masks = pbvd.group_table(K, gens)
+
+    def col(k):
+        c = 0
+        for g in gens:
+            c = (c << 1) | ((g >> k) & 1)
+        return c
+    gK, g0 = col(K - 1), col(0)
+    for j in range(1 << (K - 2)):
+        assert alpha[j] == lab[2 * j][0]
+    for a in range(1 << R):
+        assert masks[a].tolist() == [a, a ^ gK, a ^ g0, a ^ gK ^ g0]
+    assert np.bincount(alpha, minlength=1 << R).tolist() == [1 << (K - 2 - R)] * (1 << R)
+
+
+def test_group_mapping_lanes_and_server(pbvd):
+    """A group-mapped plan runs 2^R lanes per PB; the request server does not
+    take the mapping."""
+    with pbvd.Plan(7, (0o171, 0o133), 512, 42, mapping=pbvd.PBVD_MAP_GROUP) as p:
+        assert p.call_lanes(1 << 20) == 4
+    with pbvd.Plan(7, (0o133, 0o171, 0o165), 512, 42, lanes_per_pb=8, mapping=pbvd.PBVD_MAP_GROUP) as p:
+        assert p.call_lanes(1 << 10) == 8
+    with pytest.raises(pbvd.PbvdError) as ei:
+        pbvd.Server([dict(K=7, gens=(0o171, 0o133), D=64, L=42, mapping=pbvd.PBVD_MAP_GROUP)])
     assert ei.value.status == pbvd.PBVD_ENOTSUP
