@@ -272,7 +272,7 @@ def batch_matches_oracle(codes, frames, streams, host_out) -> bool:
 
 def bench_batched(torch, steps: int, fixed=None):
     """Batched decode of 4096 frames (lengths U[40, 6144], K=7 r1/2 and r1/3
-    50/50, Eb/N0 U[1, 5] dB): D tuned (or `fixed` = (D, lanes per PB)),
+    50/50, Eb/N0 U[1, 5] dB): D and layout tuned (or `fixed` = (D, layout name)),
     HIP-graph replay timed, against one plain launch per frame."""
     from paper_1608_00066_amd import autotune, datagen, pbvd
     base = [dict(K=7, gens=(0o171, 0o133), L=42), dict(K=7, gens=(0o133, 0o171, 0o165), L=42)]
@@ -282,11 +282,14 @@ def bench_batched(torch, steps: int, fixed=None):
     syms = torch.from_numpy(syms_h).cuda()
     out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
     if fixed:
-        codes, table = [dict(c, D=fixed[0], lanes_per_pb=fixed[1]) for c in base], []
+        layout = next(l for l in autotune.BATCH_LAYOUTS if l[0] == fixed[1])
+        codes, table = autotune.layout_codes(base, fixed[0], layout), []
     else:
         codes, table = autotune.tune_batch_d(torch, base, frames, syms, out)
     D = codes[0]["D"]
-    log("batched: tuned D=%d lanes=%d" % (D, codes[0]["lanes_per_pb"]))
+    layout_name = next(l[0] for l in autotune.BATCH_LAYOUTS
+                       if autotune.layout_codes(base, D, l) == codes)
+    log("batched: tuned D=%d layout=%s" % (D, layout_name))
     with pbvd.Batch(codes) as b:
         b.set_frames(frames, syms.numel(), out.numel())
         info = b.info()
@@ -334,8 +337,12 @@ def bench_batched(torch, steps: int, fixed=None):
         "batched_equals_plain_same_d": same,
         # for the oracle comparison of the CPU-baseline leg (not printed)
         "_check": (codes, frames, streams, batched.cpu().numpy()),
-        "lanes_per_pb": codes[0]["lanes_per_pb"],
-        "tuning_ms": {"D%d_lanes%d" % dl: round(t * 1e3, 4) for dl, t, _ in table},
+        "layout": layout_name,
+        "tuning_ms": {"D%d_%s" % dl: round(t * 1e3, 4) for dl, t, _ in table},
+        # the fastest D of each layout (wave: one persistent launch per K)
+        "best_by_layout": {name: {"D": dl[0], "mbps": round(n_bits / t / 1e6, 1)}
+                           for name in {dl[1] for dl, _, _ in table}
+                           for dl, t, _ in [min((r for r in table if r[0][1] == name), key=lambda r: r[1])]},
     }
 
 
@@ -377,7 +384,8 @@ def batched_summary(b):
     if not b:
         return None
     return {"value": b["batched_mbps"], "unit": "Mbps", "ms_per_step": b["batched_graph_ms"],
-            "workload": b["workload"], "D": b["D"],
+            "workload": b["workload"], "D": b["D"], "layout": b["layout"],
+            "best_by_layout": b.get("best_by_layout"),
             "roofline": {"bound": "alu", "achieved": b["batched_alu_tops"], "peak": PEAK_ALU_OPS[16] / 1e12,
                          "unit": "Tops/s", "frac": b["batched_alu_frac"]},
             "plain_per_frame_mbps": b["plain_per_frame_d512_mbps"]}
@@ -395,9 +403,14 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds of Poisson load per arrival rate in the serving measurement")
-    ap.add_argument("--only-batched", type=int, nargs=2, default=None, metavar=("D", "LANES"),
-                    help="only run the batched measurement at block length D and LANES lanes "
-                         "per PB (no tuning), print its JSON and exit (for profiling)")
+    ap.add_argument("--only-batched", nargs=2, default=None, metavar=("D", "LAYOUT"),
+                    help="only run the batched measurement at block length D and layout LAYOUT "
+                         "(lanes1, lanes2, wave, group; no tuning), print its JSON and exit "
+                         "(for profiling)")
+    ap.add_argument("--only-stream", nargs=4, default=None, metavar=("K", "LOG2_BITS", "D", "MAPPING"),
+                    help="only time pbvd_decode of one 3 dB stream (K=7 r1/2 (171,133) or K=9 r1/3 "
+                         "(557,663,711), L=6K) of 2^LOG2_BITS bits at block length D on MAPPING "
+                         "(auto, lanes, wave, group), print its JSON and exit (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB five times (to scale the "
                          "FETCH_SIZE/WRITE_SIZE counters of rocprofv3) and exit")
@@ -415,9 +428,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.only_batched:
-        res = bench_batched(torch, args.steps, tuple(args.only_batched))
+        res = bench_batched(torch, args.steps, (int(args.only_batched[0]), args.only_batched[1]))
         res.pop("_check", None)
         print(json.dumps(res), flush=True)
+        return
+    if args.only_stream:
+        k_s, lb_s, d_s = (int(x) for x in args.only_stream[:3])
+        mapping = {"auto": 0, "lanes": 1, "wave": 2, "group": 3}[args.only_stream[3]]
+        g_s = {7: (0o171, 0o133), 9: (0o557, 0o663, 0o711)}[k_s]
+        n_s = 1 << lb_s
+        st_s = datagen.make_stream(k_s, g_s, n_s, 3.0, datagen.config_seed(2, 3.0, 0 if k_s == 7 else 1))
+        d_sy = torch.from_numpy(st_s["syms"]).cuda()
+        o_s = torch.empty((n_s + 7) // 8, dtype=torch.uint8, device="cuda")
+        with pbvd.Plan(k_s, g_s, d_s, 6 * k_s, mapping=mapping) as p_s:
+            ms_s, kms_s = time_decode(torch, p_s, d_sy, n_s, o_s, args.steps, args.warmup)
+            lanes_s = p_s.call_lanes(n_s)
+        print(json.dumps({"K": k_s, "n_bits": n_s, "D": d_s, "mapping": args.only_stream[3],
+                          "lanes_per_pb": lanes_s, "ms_per_step": round(ms_s, 4),
+                          "kernel_ms": round(kms_s, 4), "mbps": round(n_s / (ms_s * 1e-3) / 1e6, 1)}),
+              flush=True)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20

@@ -49,25 +49,39 @@ def lanes_allowed(code, lanes: int) -> bool:
             and (1 << (code["K"] - 2)) // lanes >= 16)
 
 
+# Layouts the batch tuner tries: (name, lanes_per_pb, mapping).  "lanes1"
+# and "lanes2": the register kernel with one or two lanes per PB (codes that
+# do not take two keep one), one tile launch per code; "wave": the
+# state-parallel kernel, one persistent launch per K over all its codes;
+# "group": the paper's group mapping, 2^R lanes per PB.
+BATCH_LAYOUTS = (("lanes1", 1, 1), ("lanes2", 2, 1), ("wave", 64, 2), ("group", 0, 3))
+
+
+def layout_codes(codes, d, layout):
+    """codes with block length d and one of BATCH_LAYOUTS."""
+    name, lanes, mapping = layout
+    out = []
+    for c in codes:
+        l = lanes if mapping != 1 or lanes_allowed(c, lanes) else 1
+        out.append(dict(c, D=int(d), lanes_per_pb=l, mapping=mapping))
+    return out
+
+
 def tune_batch_d(torch, codes, frames, syms_dev, out_dev,
                  d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512),
-                 lane_candidates=(1, 2, 64), reps: int = 5):
-    """One D for all codes and one lane-group width per run (codes that do
-    not support it keep one lane; 64: the state-parallel kernel, one
-    persistent launch for all codes of one K), the fastest batched decode of
-    `frames`.
-    Returns (codes with D and lanes_per_pb filled in, [((D, lanes), seconds,
-    info)])."""
+                 layouts=BATCH_LAYOUTS, reps: int = 5):
+    """One D for all codes and one layout per run (block length, and how a
+    PB maps to lanes: the survivor layout follows from it), the fastest
+    batched decode of `frames`.  Returns (codes with D, lanes_per_pb and
+    mapping filled in, [((D, layout name), seconds, info)])."""
     table = []
-    for lanes in lane_candidates:
+    for layout in layouts:
         for d in d_candidates:
-            cs = [dict(c, D=int(d), lanes_per_pb=lanes if lanes_allowed(c, lanes) else 1)
-                  for c in codes]
-            t, info = time_batch(torch, cs, frames, syms_dev, out_dev, reps=reps)
-            table.append(((int(d), lanes), t, info))
+            t, info = time_batch(torch, layout_codes(codes, d, layout), frames, syms_dev, out_dev, reps=reps)
+            table.append(((int(d), layout[0]), t, info))
     (best_d, best_l) = min(table, key=lambda r: r[1])[0]
-    return [dict(c, D=best_d, lanes_per_pb=best_l if lanes_allowed(c, best_l) else 1)
-            for c in codes], table
+    layout = next(l for l in layouts if l[0] == best_l)
+    return layout_codes(codes, best_d, layout), table
 
 
 def tune_plan_lanes(torch, K, gens, D, L, syms_dev, n_bits, out_dev, reps: int = 5, **plan_kw):
@@ -115,11 +129,19 @@ def serve_load(srv, pool, rate: float, seconds: float, seed: int = 1):
     submitted = time.perf_counter()
     infos = [srv.wait(t)[1] for t in tickets]
     lat = np.array([i["latency_ns"] for i in infos], dtype=np.float64) / 1e6
+    # queue wait: submission to the launch of the batch carrying the
+    # request; service: that launch to the bits in the caller's buffer
+    wait = np.array([i["start_ns"] - i["submit_ns"] for i in infos], dtype=np.float64) / 1e6
+    service = np.array([i["done_ns"] - i["start_ns"] for i in infos], dtype=np.float64) / 1e6
     span = (max(i["done_ns"] for i in infos) - min(i["submit_ns"] for i in infos)) / 1e9
     return {"rate": rate, "requests": n, "offered_rate": round(n / (submitted - start), 1),
             "p50_ms": round(float(np.percentile(lat, 50)), 4),
             "p99_ms": round(float(np.percentile(lat, 99)), 4),
             "max_ms": round(float(lat.max()), 4),
+            "queue_wait_p50_ms": round(float(np.percentile(wait, 50)), 4),
+            "queue_wait_p99_ms": round(float(np.percentile(wait, 99)), 4),
+            "service_p50_ms": round(float(np.percentile(service, 50)), 4),
+            "service_p99_ms": round(float(np.percentile(service, 99)), 4),
             "mbps": round(bits / span / 1e6, 2),
             "mean_batch": round(float(np.mean([i["batch_frames"] for i in infos])), 2)}
 
