@@ -36,8 +36,9 @@ def noalloc(torch, pbvd, plan, dsyms, n, pb_first, pb_count, out, fpm):
     return st
 
 
-@pytest.mark.parametrize("mapping,D,offset", [(1, 512, 0), (2, 512, 0), (2, 100, 1), (1, 96, 0)],
-                         ids=["lanes", "wave", "wave-staging", "lanes-staging"])
+@pytest.mark.parametrize("mapping,D,offset", [(1, 512, 0), (2, 512, 0), (2, 100, 1), (1, 96, 0), (3, 512, 0),
+                                               (3, 100, 1)],
+                         ids=["lanes", "wave", "wave-staging", "lanes-staging", "group", "group-staging"])
 def test_noalloc_equals_decode_ex_twice(torch, pbvd, mapping, D, offset):
     K, gens, L = 7, (0o171, 0o133), 42
     print("noalloc mapping %d D=%d" % (mapping, D), flush=True)
