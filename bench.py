@@ -79,6 +79,32 @@ def settle_clocks(torch, plan, syms, n_bits, out, seconds: float = 0.08) -> int:
     return count
 
 
+def time_decode_graph(torch, plan, syms, n_bits, out, steps):
+    """ms per decode when `steps` decodes are captured in one HIP graph and
+    replayed (no host launch cost per decode: a short stream's decode is
+    shorter than the Python call that launches it)."""
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    plan.decode(syms, n_bits, out=out)  # workspace allocated outside the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            for _ in range(steps):
+                plan.decode(syms, n_bits, out=out, stream=side)
+    torch.cuda.current_stream().wait_stream(side)
+    g.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    g.replay()
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    del g
+    return ms
+
+
 def time_decode(torch, plan, syms, n_bits, out, steps, warmup):
     """Warm-up, then `steps` timed decodes.  Returns (ms per step from the
     host clock between synchronizations, mean kernel ms from HIP events on
@@ -458,11 +484,15 @@ def main():
         d_sy = torch.from_numpy(st_s["syms"]).cuda()
         o_s = torch.empty((n_s + 7) // 8, dtype=torch.uint8, device="cuda")
         with pbvd.Plan(k_s, g_s, d_s, 6 * k_s, mapping=mapping) as p_s:
+            settle_clocks(torch, p_s, d_sy, n_s, o_s)
             ms_s, kms_s = time_decode(torch, p_s, d_sy, n_s, o_s, args.steps, args.warmup)
+            msg_s = time_decode_graph(torch, p_s, d_sy, n_s, o_s, args.steps)
             lanes_s = p_s.call_lanes(n_s)
         print(json.dumps({"K": k_s, "n_bits": n_s, "D": d_s, "mapping": args.only_stream[3],
                           "lanes_per_pb": lanes_s, "ms_per_step": round(ms_s, 4),
-                          "kernel_ms": round(kms_s, 4), "mbps": round(n_s / (ms_s * 1e-3) / 1e6, 1)}),
+                          "kernel_ms": round(kms_s, 4), "mbps": round(n_s / (ms_s * 1e-3) / 1e6, 1),
+                          "graph_ms_per_step": round(msg_s, 4),
+                          "graph_mbps": round(n_s / (msg_s * 1e-3) / 1e6, 1)}),
               flush=True)
         return
     if args.copy_calibration:
@@ -512,8 +542,13 @@ def main():
                     settle_clocks(torch, p2, d_s2, n2, o2)
                 ms2, kms2 = time_decode(torch, p2, d_s2, n2, o2,
                                         200 if short else max(3, args.steps // 4), 50 if short else 20)
+                if short:
+                    msg = time_decode_graph(torch, p2, d_s2, n2, o2, 200)
             extras[tag + "_mbps"] = round(n2 / (ms2 * 1e-3) / 1e6, 1)
             extras[tag + "_kernel_ms"] = round(kms2, 4)
+            if short:
+                # 200 decodes replayed from one captured graph
+                extras[tag + "_graph_mbps"] = round(n2 / (msg * 1e-3) / 1e6, 1)
             del d_s2, o2, s2
         sweep = {}
         for d2 in (256, 1024, 2048):

@@ -37,7 +37,7 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
         const int req = requested_lb(codes[i]);
         const int top = max_lb(codes[i]);
         cs.lb[i] = req == kGroupLb ? kGroupLb
-                   : idx < 0 || (req < 0 && auto_lb == kWaveLb) ? kWaveLb
+                   : idx < 0 || (req < 0 && auto_lb == kWaveLb && codes[i].mapping != PBVD_MAP_LANES) ? kWaveLb
                    : req >= 0 ? req : (auto_lb < 0 || auto_lb > top ? top : auto_lb);
         if (cs.lb[i] == kGroupLb) (void)group_tables(cs.codes[i], &cs.gtab[i]);  // checked by check_code
     }

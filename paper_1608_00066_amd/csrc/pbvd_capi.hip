@@ -528,7 +528,8 @@ int64_t launch_limit(const pbvd_plan *p, const Workspace &ws, int64_t sp_wave_dw
 int call_lb(const pbvd_plan *p, int64_t n_bits, int64_t pb_first, int64_t pb_count) {
     const int req = requested_lb(p->code);
     if (req >= 0) return req;
-    if (p->code_idx < 0 || pb_count <= p->wave_max_pbs) return kWaveLb;
+    // PBVD_MAP_LANES keeps the register kernel whatever the PB count
+    if (p->code_idx < 0 || (p->code.mapping != PBVD_MAP_LANES && pb_count <= p->wave_max_pbs)) return kWaveLb;
     const int top = max_lb(p->code);
     if (top == 0) return 0;
     if (p->code.K <= 7 && call_geometry(p->code, n_bits, pb_first, pb_count, 0).n_waves >= 4096) return 0;

@@ -190,45 +190,6 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
     const int n_trips = (len + W - 1) / W;
     const int off = n_trips * W - len;
 
-    // ---- per-lane code-word masks of the two branches into each position,
-    //      per phase and slot (Eq. 2 with the run-time generators) ----
-    uint32_t mup[V][SL], mlo[V][SL];
-#pragma unroll
-    for (int ph = 0; ph < V; ++ph) {
-#pragma unroll
-        for (int s = 0; s < SL; ++s) {
-            const uint32_t u = (uint32_t)(s * kWave + (lane & (NL - 1)));
-            const uint32_t even = u & ~(1u << ph);
-            const uint32_t se = rotr_rt32<V>(even, ph);   // the upper predecessor S_2j
-            const uint32_t x = (u >> ph) & 1u;             // input bit of the branch
-            const uint32_t reg = (x << V) | se;
-            uint32_t mu = 0, ml = 0;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {  // generators past R are 0: zero mask bytes
-                mu |= (uint32_t)parity32(code.gen[r] & reg) << (8 * r);
-                ml |= (uint32_t)parity32(code.gen[r] & (reg | 1u)) << (8 * r);
-            }
-            mup[ph][s] = mu;
-            mlo[ph][s] = ml;
-        }
-    }
-
-    // ---- initial metrics: with a known start, state 0 (position 0 at any
-    //      phase) at 0 and the others at 8192; otherwise all 0 ----
-    int pm[SL];
-#pragma unroll
-    for (int s = 0; s < SL; ++s) {
-        const int u = s * kWave + (lane & (NL - 1));
-        pm[s] = (j.known && u != 0) ? 8192 : 0;
-    }
-
-    // path words (register exchange within a trip)
-    uint32_t hist[SL];
-#pragma unroll
-    for (int s = 0; s < SL; ++s) hist[s] = 0;
-
-    uint32_t *const sp_lane = sp_wave + lane;  // [trip][slot][lane]
-
     // Symbols: the R symbols of stage t are packed in one dword (bytes
     // 0..R-1; the bytes above belong to the next stage and meet zero mask
     // bytes).  Lane l holds those of the trip's stage g*16 + (l mod 16) in
@@ -275,6 +236,52 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
         else asm volatile("s_nop 1" : "+v"(qv[0]), "+v"(qv[1]));
     };
 
+    // the first trip's symbols are requested before the masks are formed
+    // (with one slot: with more, the masks' registers leave no room)
+    uint32_t nlo[G], nhi[G], nmis[G];
+    if constexpr (SL == 1) load_q(nlo, nhi, nmis, -off);
+
+    // ---- per-lane code-word masks of the two branches into each position,
+    //      per phase and slot (Eq. 2 with the run-time generators) ----
+    uint32_t mup[V][SL], mlo[V][SL];
+#pragma unroll
+    for (int ph = 0; ph < V; ++ph) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) {
+            const uint32_t u = (uint32_t)(s * kWave + (lane & (NL - 1)));
+            const uint32_t even = u & ~(1u << ph);
+            const uint32_t se = rotr_rt32<V>(even, ph);   // the upper predecessor S_2j
+            const uint32_t x = (u >> ph) & 1u;             // input bit of the branch
+            const uint32_t reg = (x << V) | se;
+            uint32_t mu = 0, ml = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {  // generators past R are 0: zero mask bytes
+                mu |= (uint32_t)parity32(code.gen[r] & reg) << (8 * r);
+                ml |= (uint32_t)parity32(code.gen[r] & (reg | 1u)) << (8 * r);
+            }
+            mup[ph][s] = mu;
+            mlo[ph][s] = ml;
+        }
+    }
+
+    if constexpr (SL > 1) load_q(nlo, nhi, nmis, -off);
+
+    // ---- initial metrics: with a known start, state 0 (position 0 at any
+    //      phase) at 0 and the others at 8192; otherwise all 0 ----
+    int pm[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) {
+        const int u = s * kWave + (lane & (NL - 1));
+        pm[s] = (j.known && u != 0) ? 8192 : 0;
+    }
+
+    // path words (register exchange within a trip)
+    uint32_t hist[SL];
+#pragma unroll
+    for (int s = 0; s < SL; ++s) hist[s] = 0;
+
+    uint32_t *const sp_lane = sp_wave + lane;  // [trip][slot][lane]
+
     // one trellis stage, the k-th of its trip (phase k mod V); each
     // candidate is its predecessor's metric plus the branch metric, the dot
     // product accumulating onto the exchanged metric; the path words follow
@@ -312,11 +319,34 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
         }
     };
 
+    // The traceback reads the path words of trips trip_bot..n_trips-1
+    // through a ring of kRing trips.  With one slot, the words of the last
+    // trip stay in registers and the loads of the trips below it are issued
+    // at the start of the last forward trip, so that they have arrived when
+    // the traceback starts.
+    const int trip_bot = (j.store0 + off) / W;
+    constexpr int kRing = SL == 1 ? 8 : SL == 2 ? 6 : 4;
+    constexpr bool kEarlyRing = SL == 1;
+    uint32_t ring[kRing][SL];
+    auto load_trip = [&](uint32_t (&dst)[SL], int trip) PBVD_INLINE_LAMBDA {
+        trip = trip < trip_bot ? trip_bot : trip;
+#pragma unroll
+        for (int s = 0; s < SL; ++s) dst[s] = __builtin_nontemporal_load(sp_lane + (trip * SL + s) * kWave);
+    };
+
     // ---- forward procedure (Eq. 1) ----
-    uint32_t nlo[G], nhi[G], nmis[G];
-    load_q(nlo, nhi, nmis, -off);
     for (int trip = 0; trip < n_trips; ++trip) {
         const int tt0 = trip * W - off;  // stage of the trip's step 0
+        if constexpr (kEarlyRing) {
+            if (trip + 1 == n_trips) {
+                // trips below the last one are stored already (a clamped
+                // load of the last trip itself is never used)
+                static_for<1, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+                    load_trip(ring[decltype(dc)::value], trip - decltype(dc)::value);
+                    return true;
+                });
+            }
+        }
         uint32_t qv[G];
         make_q(nlo, nhi, nmis, qv);
         if (trip + 1 < n_trips) load_q(nlo, nhi, nmis, tt0 + W);  // a trip ahead
@@ -380,7 +410,6 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
     // ones are merged into the output word under assembly.
     const int store0 = j.store0, dec_end = j.dec_end;
     const int n_dec = dec_end - store0;
-    const int trip_bot = (store0 + off) / W;
     int cm = (n_dec - 1) >> 5;  // output word under assembly (relative to the PB)
     uint32_t cw = 0;
 
@@ -408,14 +437,6 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
         }
     };
 
-    // path words of a trip, loaded a ring of trips ahead
-    constexpr int kRing = SL == 1 ? 8 : SL == 2 ? 6 : 4;
-    uint32_t ring[kRing][SL];
-    auto load_trip = [&](uint32_t (&dst)[SL], int trip) PBVD_INLINE_LAMBDA {
-        trip = trip < trip_bot ? trip_bot : trip;
-#pragma unroll
-        for (int s = 0; s < SL; ++s) dst[s] = __builtin_nontemporal_load(sp_lane + (trip * SL + s) * kWave);
-    };
     auto run_trip = [&](const uint32_t (&hw)[SL], int trip) PBVD_INLINE_LAMBDA {
         uint32_t h;
         if constexpr (SL == 1) {
@@ -460,10 +481,15 @@ __device__ __forceinline__ void decode_pb(const Args &a, const Job &j, const Wav
     };
 
     const int trip_top = n_trips - 1;
-    static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
-        load_trip(ring[decltype(dc)::value], trip_top - decltype(dc)::value);
-        return true;
-    });
+    if constexpr (kEarlyRing) {
+#pragma unroll
+        for (int s = 0; s < SL; ++s) ring[0][s] = hist[s];
+    } else {
+        static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+            load_trip(ring[decltype(dc)::value], trip_top - decltype(dc)::value);
+            return true;
+        });
+    }
     int trip = trip_top;
     for (;;) {
         const bool more = static_for<0, kRing>([&](auto dc) PBVD_INLINE_LAMBDA {

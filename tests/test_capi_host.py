@@ -102,6 +102,13 @@ def test_auto_mapping_rule(pbvd, monkeypatch):
         assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1 << 27, 0, 1 << 18) == 1
     finally:
         pbvd.pbvd_destroy(h)
+    # PBVD_MAP_LANES keeps the register kernel for calls of few PBs too
+    h = pbvd.pbvd_create(7, (0o171, 0o133), 512, 42, mapping=pbvd.PBVD_MAP_LANES)
+    try:
+        assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1 << 20, 0, 2048) in (1, 2)
+        assert L.pbvd_call_lanes(ctypes.c_void_p(h), 1500, 0, 3) in (1, 2)
+    finally:
+        pbvd.pbvd_destroy(h)
     monkeypatch.setenv("PBVD_WAVE_MAX_PBS", "0")
     h = pbvd.pbvd_create(7, (0o171, 0o133), 512, 42)
     try:
