@@ -68,17 +68,32 @@ def layout_codes(codes, d, layout):
 
 
 def tune_batch_d(torch, codes, frames, syms_dev, out_dev,
-                 d_candidates=(48, 64, 80, 96, 112, 128, 160, 192, 256, 512),
-                 layouts=BATCH_LAYOUTS, reps: int = 5):
+                 d_candidates=(48, 64, 96, 128, 160, 192, 224, 256, 320, 512),
+                 layouts=BATCH_LAYOUTS, reps: int = 5, refine: int = 2):
     """One D for all codes and one layout per run (block length, and how a
     PB maps to lanes: the survivor layout follows from it), the fastest
-    batched decode of `frames`.  Returns (codes with D, lanes_per_pb and
-    mapping filled in, [((D, layout name), seconds, info)])."""
+    batched decode of `frames`: a coarse grid of D for every layout, then D
+    in steps of 8 within 24 of the `refine` best (D, layout) pairs (the time
+    is not smooth in D: the number of tiles against the number of SIMDs and
+    each PB's trip alignment both change with it).  Returns (codes with D,
+    lanes_per_pb and mapping filled in, [((D, layout name), seconds,
+    info)])."""
     table = []
+    seen = set()
+
+    def run(d, layout):
+        if (d, layout[0]) in seen or d < 8:
+            return
+        seen.add((d, layout[0]))
+        t, info = time_batch(torch, layout_codes(codes, d, layout), frames, syms_dev, out_dev, reps=reps)
+        table.append(((int(d), layout[0]), t, info))
     for layout in layouts:
         for d in d_candidates:
-            t, info = time_batch(torch, layout_codes(codes, d, layout), frames, syms_dev, out_dev, reps=reps)
-            table.append(((int(d), layout[0]), t, info))
+            run(int(d), layout)
+    for (d, name), _, _ in sorted(table, key=lambda r: r[1])[:refine]:
+        layout = next(l for l in layouts if l[0] == name)
+        for dd in range(d - 24, d + 25, 8):
+            run(dd, layout)
     (best_d, best_l) = min(table, key=lambda r: r[1])[0]
     layout = next(l for l in layouts if l[0] == best_l)
     return layout_codes(codes, best_d, layout), table
