@@ -260,11 +260,20 @@ void pbvd_destroy(pbvd_plan *p);
 /* ---- Batched decoding: many independent frames, several codes ----------
  *
  * A batch decodes many frames (each a separate stream in the sense of
- * Sec. III-A: its own PBs, its own start and end) in one launch per code.
- * The PBs of all frames of a code are packed 64 to a wave regardless of
- * frame boundaries, so thousands of short frames fill the GPU as well as one
- * long stream does.  Every frame's output is identical to decoding that
- * frame alone with pbvd_decode and the same code parameters. */
+ * Sec. III-A: its own PBs, its own start and end).  The PBs of all frames
+ * are packed regardless of frame boundaries, so thousands of short frames
+ * fill the GPU as well as one long stream does; per code mapping:
+ *   register kernel (PBVD_MAP_LANES / AUTO): tiles of 64 >> lb PBs of one
+ *     code, one launch per code;
+ *   state-parallel kernel (PBVD_MAP_WAVE): the PBs of every such code of one
+ *     K in ONE persistent launch, longest first, waves taking PBs from work
+ *     counters (one per XCD) that a fill kernel zeroes at the start of each
+ *     decode;
+ *   group mapping (PBVD_MAP_GROUP): tiles of 64 PBs, one launch per code.
+ * The launches run on forked streams.  Every frame's output is identical to
+ * decoding that frame alone with pbvd_decode and the same code parameters.
+ * Decodes of one batch must not overlap each other (they share the survivor
+ * area and the work counters): issue them on one stream. */
 
 typedef struct pbvd_batch pbvd_batch;
 
@@ -297,10 +306,12 @@ pbvd_status pbvd_batch_create(const pbvd_code *codes, int32_t n_codes, pbvd_batc
 pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64_t n_frames,
                                   int64_t sym_bytes, int64_t out_bytes);
 
-/* Decode the frames last given to pbvd_batch_set_frames: one kernel launch
- * per code, asynchronous on hip_stream.  It allocates nothing and copies
- * nothing from the host, so it can be captured in a HIP graph and replayed.
- * Bytes of d_out outside the frames' output ranges are not written. */
+/* Decode the frames last given to pbvd_batch_set_frames (Sec. III-A per
+ * frame): the launches above, asynchronous on hip_stream.  It allocates
+ * nothing, copies nothing from the host and records no memset (the work
+ * counters are reset by a kernel), so it can be captured in a HIP graph and
+ * replayed.  Bytes of d_out outside the frames' output ranges are not
+ * written.  PBVD_EINVAL for NULL buffers, PBVD_EHIP for a failed launch. */
 pbvd_status pbvd_batch_decode(pbvd_batch *b, const void *d_syms, uint8_t *d_out, void *hip_stream);
 
 /* Work-list statistics of the current frames: tiles (waves), parallel blocks,
