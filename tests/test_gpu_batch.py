@@ -245,13 +245,39 @@ def test_batch_mapping_per_code(torch, pbvd, mapping):
 
 def test_batch_codes_outside_the_registry(torch, pbvd):
     """Codes without a register kernel batch on the state-parallel kernel
-    next to registered ones, in one batch, graph-capturable."""
+    (persistent launches, one per K) next to registered ones on tiles and on
+    the group mapping, in one batch; the decode replays from a captured HIP
+    graph with the same bytes."""
     codes = [dict(K=7, gens=(0o171, 0o133), D=128, L=42),
              dict(K=6, gens=(0o53, 0o56, 0o76, 0o64), D=64, L=30),       # not registered
              dict(K=8, gens=(0o237, 0o350, 0o222), D=96, L=48, terminated=False),  # not registered
-             dict(K=5, gens=(0o31, 0o6), D=40, L=25, input_kind=1)]      # not registered
-    log("batch: registered + unregistered codes, 200 frames")
-    check_batch(torch, pbvd, codes, 200, 1, 2500, seed=81)
+             dict(K=5, gens=(0o31, 0o6), D=40, L=25, input_kind=1),      # not registered
+             dict(K=8, gens=(0o247, 0o371), D=64, L=48, mapping=2),      # same K, one launch
+             dict(K=7, gens=(0o133, 0o171, 0o165), D=72, L=42, mapping=3)]
+    log("batch: registered + unregistered codes, three layouts, 200 frames")
+    frames, streams, syms, out_bytes, _ = check_batch(torch, pbvd, codes, 200, 1, 2500, seed=81)
+    d_syms = torch.from_numpy(syms).cuda()
+    out = torch.zeros(out_bytes, dtype=torch.uint8, device="cuda")
+    with pbvd.Batch(codes) as b:
+        b.set_frames(frames, syms.size, out_bytes)
+        b.decode(d_syms, out)
+        torch.cuda.synchronize()
+        eager = out.clone()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                b.decode(d_syms, out)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            out.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager)
+        del g
 
 
 @pytest.mark.parametrize("waves", [1, 5, 64])
