@@ -170,16 +170,18 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
         }
         const size_t pw = (size_t)(pbvd::kWave >> lb);  // PBs per tile
         std::vector<PbRec> &v = per_code[ci];
-        // longest first (load balance); PBs that start their traceback from
-        // the best state must share a tile with PBs of the same length only,
-        // so that all of a tile's final metrics are taken at one stage
-        // (equal geometries next to each other, so that most tiles hold PBs
-        // of one geometry and run the kernel's uniform-wave path)
+        // PBs that start their traceback from the best state must share a
+        // tile with PBs of the same length only, so that all of a tile's
+        // final metrics are taken at one stage.  The others by first traced
+        // stage, then longest first (load balance): equal geometries next to
+        // each other, so that most tiles hold PBs of one geometry and run the
+        // kernel's uniform-wave path, and tiles of PBs of different lengths
+        // mostly share their first traced stage (phase-aligned traceback).
         std::stable_sort(v.begin(), v.end(), [](const PbRec &x, const PbRec &y) {
             const bool ax = x.flags & pbvd::kLaneArgmin, ay = y.flags & pbvd::kLaneArgmin;
             if (ax != ay) return ax < ay;
-            if (x.len != y.len) return x.len > y.len;
             if (x.store0 != y.store0) return x.store0 < y.store0;
+            if (x.len != y.len) return x.len > y.len;
             return x.dec_end < y.dec_end;
         });
         wl->groups[ci].tile_begin = (int64_t)wl->heads.size();
@@ -191,14 +193,17 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 while (k < e && (v[k].flags & pbvd::kLaneArgmin) && v[k].len == v[i].len) ++k;
                 e = k;
             } else {
+                // a tile ends where the first traced stage changes: its PBs
+                // share it, so that tiles of PBs of different lengths take
+                // the phase-aligned traceback
                 size_t k = i + 1;
-                while (k < e && !(v[k].flags & pbvd::kLaneArgmin)) ++k;
+                while (k < e && !(v[k].flags & pbvd::kLaneArgmin) && v[k].store0 == v[i].store0) ++k;
                 e = k;
             }
             pbvd::TileHead h{};
             h.len = 0;
             h.store0_min = 0x7fffffff;
-            bool wide = true, final_needed = false, uniform = true;
+            bool wide = true, final_needed = false, uniform = true, same_store0 = true;
             for (size_t k = i; k < i + pw; ++k) {
                 // PBs past the tile's repeat its first PB, inactive; every
                 // lane of a PB's group gets the PB's descriptor
@@ -212,6 +217,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 d.flags = k < e ? r.flags : (r.flags & ~pbvd::kLaneActive);
                 for (int g = 0; g < (1 << lb); ++g) wl->lanes.push_back(d);
                 if (r.len != v[i].len || r.store0 != v[i].store0 || r.dec_end != v[i].dec_end) uniform = false;
+                if (r.store0 != v[i].store0) same_store0 = false;
                 if (r.len > h.len) h.len = r.len;
                 if (r.store0 < h.store0_min) h.store0_min = r.store0;
                 const int64_t last_trip = ((r.len - 1) / U) * U;
@@ -219,7 +225,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 if (r.flags & pbvd::kLaneArgmin) final_needed = true;
             }
             h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0) |
-                      (uniform ? pbvd::kTileUniform : 0);
+                      (uniform ? pbvd::kTileUniform : 0) | (same_store0 ? pbvd::kTileStore0 : 0);
             wl->heads.push_back(h);
             i = e;
         }

@@ -269,7 +269,11 @@ constexpr int kBufferFlags = 0x00020000;  // raw 32-bit data format (gfx9 family
 constexpr int kRowPolicy = 2;  // nt
 
 // A lane moves NDW dwords of a row; consecutive rows are ROW_DW dwords apart
-// (64 lanes x their own dwords when every lane stores its part).
+// (64 lanes x their own dwords when every lane stores its part).  Stores move
+// at most 8 bytes per lane: the vector memory unit reads the data registers
+// of a wider store over several cycles after it issues, and an instruction
+// that overwrites them too soon (which the compiler does not always prevent)
+// changes what the last lanes store.  8-byte stores have no such window.
 template <int NDW, int ROW_DW = kWave * NDW>
 struct RowStore {
     __amdgpu_buffer_rsrc_t rsrc;
@@ -279,13 +283,11 @@ struct RowStore {
         const int so = row * kRowBytes;
         if constexpr (NDW == 1) {
             __builtin_amdgcn_raw_buffer_store_b32(v[0], rsrc, lane_off, so, kRowPolicy);
-        } else if constexpr (NDW == 2) {
-            __builtin_amdgcn_raw_buffer_store_b64(u32x2{v[0], v[1]}, rsrc, lane_off, so, kRowPolicy);
         } else {
 #pragma unroll
-            for (int w = 0; w < NDW; w += 4)
-                __builtin_amdgcn_raw_buffer_store_b128(u32x4{v[w], v[w + 1], v[w + 2], v[w + 3]}, rsrc,
-                                                       lane_off + 4 * w, so, kRowPolicy);
+            for (int w = 0; w < NDW; w += 2)
+                __builtin_amdgcn_raw_buffer_store_b64(u32x2{v[w], v[w + 1]}, rsrc, lane_off + 4 * w, so,
+                                                      kRowPolicy);
         }
     }
     __device__ __forceinline__ void load(int row, uint32_t (&v)[NDW]) const {
@@ -542,6 +544,7 @@ struct WaveJob {
     bool known;          // start from encoder state 0
     bool argmin;         // trace back from the least-metric state
     bool active;
+    bool store0_uniform; // VARLEN: every lane's first traced stage is store0_min
     int64_t out_bit0;    // output bit position of the lane's first decoded bit
     int32_t *pm_out;     // final-metric row or null
 };
@@ -673,10 +676,34 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
     for (int w = 0; w < NDW; ++w) dw[w] = 0;
     int trips_since_renorm = 0;
     int i0 = 0;
+    // Straight-line trips: whole trips whose next fetch is in bounds need no
+    // per-stage checks; the generic loop below finishes the block.
+    const int fast_end = len - U < j.i_safe - U ? len - U : j.i_safe - U;
+    // Trips that lie wholly before the lowest traced stage (the L warm-up
+    // stages of Sec. III-A) store no rows: the traceback never reads them,
+    // so their decision bits are not even formed.
+    const int warm_end = j.store0_min / U * U < fast_end ? j.store0_min / U * U : fast_end;
+    for (; i0 < warm_end; i0 += U) {
+        fetch(raw_next, sh_next, i0 + U, true);
+        if (++trips_since_renorm == LY::kRenormTrips) {
+            trips_since_renorm = 0;
+            renorm();
+        }
+        static_for<0, U>([&](auto kc) PBVD_INLINE_LAMBDA {
+            constexpr int k = decltype(kc)::value;
+            int q[R], bm[NC];
+            symbols(wsym, k, q);
+            stage_metrics(std::integral_constant<int, k % V>{}, q, bm);
+            acs_stage<C, P, k % V, (k % S) * NR, NDW, LY::kBytePerm, LB>(pm, bm, dw);
+            if constexpr ((k % S) == S - 1) {
+#pragma unroll
+                for (int w = 0; w < NDW; ++w) dw[w] = 0;
+            }
+            return true;
+        });
+        align_trip(raw_next, sh_next, wsym);
+    }
     if constexpr (LY::kFastLoop) {
-        // Straight-line trips: whole trips whose next fetch is in bounds need
-        // no per-stage checks; the generic loop below finishes the block.
-        const int fast_end = len - U < j.i_safe - U ? len - U : j.i_safe - U;
         for (; i0 < fast_end; i0 += U) {
             fetch(raw_next, sh_next, i0 + U, true);
             if (++trips_since_renorm == LY::kRenormTrips) {
@@ -887,79 +914,99 @@ __device__ __forceinline__ void decode_body(const WaveJob &j, const RowStore<Lay
         idx = (idx & ~m) | ((dec << qpos) & m);
     };
 
-    if constexpr (!VARLEN && S == 1) {
-        // ---- one stage per row and one geometry for the whole wave: blocks
-        //      of V rows whose top row is at phase V-1, so every step's bit
-        //      position is a compile-time constant; only the first and the
-        //      last block (and the one holding the decoded range's end) check
-        //      stage bounds. ----
-        constexpr int TB = V;
-        constexpr int kRing = PBVD_TRACEBACK_RING_VGPRS / (TB * W) < 2 ? 2
-                            : PBVD_TRACEBACK_RING_VGPRS / (TB * W) > 12 ? 12
-                            : PBVD_TRACEBACK_RING_VGPRS / (TB * W);
-        const int i_top = len - 1;
-        const int dec_end = j.my_dec_end;  // decoded stages are [i_lo, dec_end)
-        // take the input bit of stage i (decoded range) into the output word;
-        // a word is complete at a multiple of 32 from the range's start
-        auto take_bit = [&](int i, uint32_t qpos, bool emit) PBVD_INLINE_LAMBDA {
-            word = (word << 1) | ((idx >> qpos) & 1u);
-            if (__builtin_expect(emit, 0)) {  // one step in 32: keep it off the straight path
-                const int rel = i - i_lo;
-                if (writer) put_word(rel, n_dec - rel < 32 ? n_dec - rel : 32);
-                word = 0;
-            }
-        };
-        // KIND 0: every stage is traced and decoded; 1: none is decoded;
-        // 2: bounds and the decoded range's end are checked stage by stage
-        auto run = [&](auto kc, const uint32_t (&blk)[TB][W], int top) PBVD_INLINE_LAMBDA {
-            constexpr int kind = decltype(kc)::value;
-            const int e = (top - i_lo) & 31;  // step whose bit completes a word
-            static_for<0, TB>([&](auto tc) PBVD_INLINE_LAMBDA {
-                constexpr int t = decltype(tc)::value;
-                constexpr uint32_t qpos = ubit_pos<V, LY::kBytePerm>(V - 1 - t);
-                const int i = top - t;
-                if constexpr (kind == 2) {
-                    if (i > i_top || i < i_lo) return true;
-                    if (i < dec_end) take_bit(i, qpos, e == t);
-                } else if constexpr (kind == 0) {
-                    take_bit(i, qpos, e == t);
+    if constexpr (S == 1) {
+        if (!VARLEN || j.store0_uniform) {
+            // ---- one stage per row and one first traced stage for the whole
+            //      wave: blocks of V rows whose top row is at phase V-1, so every
+            //      step's bit position is a compile-time constant; only the first
+            //      and the last block (and the one holding the decoded range's
+            //      end) check stage bounds.  With VARLEN each lane holds its start
+            //      state until the traceback reaches its own last stage and takes
+            //      bits only below its own decoded range's end (selects, no
+            //      branches), so tiles of PBs of different lengths trace back at
+            //      the rate of one geometry. ----
+            constexpr int TB = V;
+            constexpr int kRing = PBVD_TRACEBACK_RING_VGPRS / (TB * W) < 2 ? 2
+                                : PBVD_TRACEBACK_RING_VGPRS / (TB * W) > 12 ? 12
+                                : PBVD_TRACEBACK_RING_VGPRS / (TB * W);
+            const int i_top = len - 1;
+            const int dec_end = j.my_dec_end;  // decoded stages are [i_lo, dec_end)
+            // take the input bit of stage i (decoded range) into the output word;
+            // a word is complete at a multiple of 32 from the range's start
+            auto take_bit = [&](int i, uint32_t qpos, bool emit) PBVD_INLINE_LAMBDA {
+                const uint32_t nw = (word << 1) | ((idx >> qpos) & 1u);
+                if constexpr (VARLEN) word = i < dec_end ? nw : word;
+                else word = nw;
+                if (__builtin_expect(emit, 0)) {  // one step in 32: keep it off the straight path
+                    const int rel = i - i_lo;
+                    const int m = n_dec - rel < 32 ? n_dec - rel : 32;
+                    if (writer && (!VARLEN || m > 0)) put_word(rel, m);
+                    word = 0;
                 }
-                follow(blk[t], 0, qpos);
+            };
+            // a lane follows the survivors only below its own last stage
+            auto follow_row = [&](const uint32_t (&row)[W], int i, uint32_t qpos) PBVD_INLINE_LAMBDA {
+                if constexpr (VARLEN) {
+                    const uint32_t held = idx;
+                    follow(row, 0, qpos);
+                    idx = i < j.my_len ? idx : held;
+                } else {
+                    follow(row, 0, qpos);
+                }
+            };
+            // KIND 0: every stage is traced and decoded; 1: none is decoded;
+            // 2: bounds and the decoded range's end are checked stage by stage
+            auto run = [&](auto kc, const uint32_t (&blk)[TB][W], int top) PBVD_INLINE_LAMBDA {
+                constexpr int kind = decltype(kc)::value;
+                const int e = (top - i_lo) & 31;  // step whose bit completes a word
+                static_for<0, TB>([&](auto tc) PBVD_INLINE_LAMBDA {
+                    constexpr int t = decltype(tc)::value;
+                    constexpr uint32_t qpos = ubit_pos<V, LY::kBytePerm>(V - 1 - t);
+                    const int i = top - t;
+                    if constexpr (kind == 2) {
+                        if (i > i_top || i < i_lo) return true;
+                        if (VARLEN || i < dec_end) take_bit(i, qpos, e == t);
+                    } else if constexpr (kind == 0) {
+                        take_bit(i, qpos, e == t);
+                    }
+                    follow_row(blk[t], i, qpos);
+                    return true;
+                });
+            };
+            auto load_rows = [&](uint32_t (&dst)[TB][W], int top) PBVD_INLINE_LAMBDA {
+    #pragma unroll
+                for (int t = 0; t < TB; ++t) {
+                    int row = top - t;
+                    row = row > row_hi ? row_hi : (row < row_lo ? row_lo : row);
+                    tb_rows.load(row, dst[t]);
+                }
+            };
+            uint32_t ring[kRing][TB][W];
+            int top = i_top + (V - 1) - i_top % V;  // the first block's top row (phase V-1)
+            static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
+                load_rows(ring[decltype(dc)::value], top - decltype(dc)::value * TB);
                 return true;
             });
-        };
-        auto load_rows = [&](uint32_t (&dst)[TB][W], int top) PBVD_INLINE_LAMBDA {
-#pragma unroll
-            for (int t = 0; t < TB; ++t) {
-                int row = top - t;
-                row = row > row_hi ? row_hi : (row < row_lo ? row_lo : row);
-                tb_rows.load(row, dst[t]);
+            for (;;) {
+                const bool more = static_for<0, kRing>([&](auto dc) PBVD_INLINE_LAMBDA {
+                    constexpr int d = decltype(dc)::value;
+                    load_rows(ring[(d + kRing - 1) % kRing], top - (kRing - 1) * TB);
+                    const int bot = top - TB + 1;
+                    // (VARLEN: the decoded range's end is checked in every step)
+                    if (top > i_top || bot < i_lo || (!VARLEN && top >= dec_end && bot < dec_end))
+                        run(std::integral_constant<int, 2>{}, ring[d], top);
+                    else if (VARLEN || top < dec_end)
+                        run(std::integral_constant<int, 0>{}, ring[d], top);
+                    else
+                        run(std::integral_constant<int, 1>{}, ring[d], top);
+                    if (bot <= i_lo) return false;
+                    top -= TB;
+                    return true;
+                });
+                if (!more) break;
             }
-        };
-        uint32_t ring[kRing][TB][W];
-        int top = i_top + (V - 1) - i_top % V;  // the first block's top row (phase V-1)
-        static_for<0, kRing - 1>([&](auto dc) PBVD_INLINE_LAMBDA {
-            load_rows(ring[decltype(dc)::value], top - decltype(dc)::value * TB);
-            return true;
-        });
-        for (;;) {
-            const bool more = static_for<0, kRing>([&](auto dc) PBVD_INLINE_LAMBDA {
-                constexpr int d = decltype(dc)::value;
-                load_rows(ring[(d + kRing - 1) % kRing], top - (kRing - 1) * TB);
-                const int bot = top - TB + 1;
-                if (top > i_top || bot < i_lo || (top >= dec_end && bot < dec_end))
-                    run(std::integral_constant<int, 2>{}, ring[d], top);
-                else if (top < dec_end)
-                    run(std::integral_constant<int, 0>{}, ring[d], top);
-                else
-                    run(std::integral_constant<int, 1>{}, ring[d], top);
-                if (bot <= i_lo) return false;
-                top -= TB;
-                return true;
-            });
-            if (!more) break;
+            return;
         }
-        return;
     }
 
     // one traceback step at stage i with that stage's survivor row
@@ -1108,6 +1155,7 @@ __global__ void __launch_bounds__(256)
         j.known = f0 == 0;
         j.argmin = false;
         j.active = active;
+        j.store0_uniform = false;
         j.out_bit0 = (b - a.pb_first) * D;
         j.pm_out = nullptr;
         decode_body<C, P, KIND, true, LB>(j, rows);
@@ -1158,6 +1206,7 @@ __global__ void __launch_bounds__(256)
     j.argmin = f1w == a.T && !a.terminated;
     j.need_final = j.argmin || a.final_pm != nullptr;
     j.active = active;
+    j.store0_uniform = true;
     j.out_bit0 = (b - a.pb_first) * D;
     j.pm_out = a.final_pm ? a.final_pm + (b - a.pb_first) * N : nullptr;
     decode_body<C, P, KIND, false, LB>(j, rows);
@@ -1184,8 +1233,10 @@ struct TileHead {
 };
 enum { kLaneKnown = 1, kLaneArgmin = 2, kLaneActive = 4 };
 // kTileUniform: every lane has the same len, store0 and dec_end, so the tile
-// runs the uniform-wave decode body (phase-aligned traceback)
-enum { kTileWide = 1, kTileFinal = 2, kTileUniform = 4 };
+// runs the uniform-wave decode body (phase-aligned traceback); kTileStore0:
+// every lane has the same store0 (lengths may differ), so the tile's
+// traceback is phase-aligned too, with a per-lane start and end
+enum { kTileWide = 1, kTileFinal = 2, kTileUniform = 4, kTileStore0 = 8 };
 
 struct TileArgs {
     const uint8_t *syms;
@@ -1227,6 +1278,7 @@ __global__ void __launch_bounds__(256)
     j.known = (d.flags & kLaneKnown) != 0;
     j.argmin = (d.flags & kLaneArgmin) != 0;
     j.active = (d.flags & kLaneActive) != 0;
+    j.store0_uniform = (tflags & kTileStore0) != 0;
     j.out_mode = kOutBytes;
     j.out = a.out;
     j.out_bytes = 0;

@@ -76,8 +76,10 @@ int64_t argmin_pbs(const pbvd_code &c, int64_t n_bits) {
 }
 
 // Bytes a set of requests needs in one slot.  Tile count per code, an upper
-// bound of what build_work_list makes: the other PBs fill whole waves, and
-// every best-state-start PB is counted as a tile of its own (they share
+// bound of what build_work_list makes: the other PBs fill whole waves, plus
+// one partial tile at each change of the first traced stage (PBs b with
+// b*D < L start at stage b*D, the others at L: at most ceil(L/D) changes),
+// and every best-state-start PB is counted as a tile of its own (they share
 // tiles only with PBs of the same length).
 struct Footprint {
     int64_t sym = 0, out = 0, frames = 0;
@@ -95,7 +97,8 @@ struct Footprint {
     // kernel (kWaveLb) takes one PB per wave and one descriptor per PB
     int64_t tiles(int ci, const CodeSet &cs) const {
         if (cs.lb[ci] == kWaveLb) return pbs[ci] + argmin[ci];
-        return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + argmin[ci];
+        const int64_t splits = pbs[ci] > 0 ? ceil_div((int64_t)cs.codes[ci].L, cs.codes[ci].D) : 0;
+        return ceil_div(pbs[ci], pbvd::kWave >> cs.lb[ci]) + splits + argmin[ci];
     }
     int64_t lanes_bytes(const CodeSet &cs) const {
         int64_t t = 0;

@@ -129,17 +129,42 @@ def test_server_admission_counts_every_best_state_block(pbvd):
     codes = [dict(K=9, gens=(0o557, 0o663, 0o711), D=16, L=54, terminated=False)]
     rng = np.random.default_rng(505)
     reqs = []
-    for i in range(120):
+    for i in range(200):
         n = int(rng.integers(150, 450))
         reqs.append((0, datagen.make_stream(9, codes[0]["gens"], n, float(rng.uniform(1, 5)),
                                             seed=6000 + i, terminated=False)))
-    log("server: 120 unterminated K=9 frames, D=16 L=54, 3 MiB per batch")
-    with pbvd.Server(codes, device_bytes=6 << 20, max_inflight=2, max_batch_frames=4096) as srv:
+    # one slot: the requests submitted while a batch runs all wait for the
+    # next one, so batches grow to what the budget admits
+    log("server: 200 unterminated K=9 frames, D=16 L=54, 3 MiB per batch, one slot")
+    with pbvd.Server(codes, device_bytes=3 << 20, max_inflight=1, max_batch_frames=4096) as srv:
         tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
         res = [srv.wait(t) for t in tickets]
         cnt = srv.counters()
         log("counters %s" % cnt)
     assert max(i["batch_frames"] for _, i in res) > 8
+    for (ci, st), (out, _) in zip(reqs, res):
+        assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st))
+
+
+def test_server_admission_counts_register_tiles(pbvd):
+    """The same on the register kernel (one lane per PB, 64 PBs per tile):
+    unterminated K=7 frames with D < L, whose PBs start their traceback at
+    four different stages (0, 16, 32, L = 42; a tile holds PBs of one first
+    traced stage) and end in four best-state-start PBs each.  Admission must
+    count every such tile, so no batch fails for want of survivor memory."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=16, L=42, terminated=False, mapping=1, lanes_per_pb=1)]
+    rng = np.random.default_rng(506)
+    reqs = []
+    for i in range(160):
+        n = int(rng.integers(100, 400))
+        reqs.append((0, datagen.make_stream(7, codes[0]["gens"], n, float(rng.uniform(1, 5)),
+                                            seed=6500 + i, terminated=False)))
+    log("server: 160 unterminated K=7 frames on the register kernel, D=16 L=42, 2 MiB per batch")
+    with pbvd.Server(codes, device_bytes=2 << 20, max_inflight=1, max_batch_frames=4096) as srv:
+        tickets = [srv.submit(ci, st["syms"], st["n"]) for ci, st in reqs]
+        res = [srv.wait(t) for t in tickets]
+        log("counters %s" % srv.counters())
+    assert max(i["batch_frames"] for _, i in res) > 1
     for (ci, st), (out, _) in zip(reqs, res):
         assert np.array_equal(unpack(out, st["n"]), oracle_bits(codes[ci], st))
 

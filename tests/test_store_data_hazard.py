@@ -1,20 +1,19 @@
-"""The 12- and 16-byte survivor-row stores keep their data VGPRs untouched
-for the wait states the hardware needs after they issue.
+"""Survivor rows are stored with at most 8 bytes per lane and store.
 
 The vector memory unit reads the data registers of a store of more than
-8 bytes after the store issues; on this GPU family an instruction that
-writes them needs two wait states after the store (two other instructions
-or an s_nop in between; the compiler's hazard recognizer inserts that much
-for the stores it schedules).  A write of them at once was measured on
-MI355X with a row layout whose stores were followed directly by such a
-write: the lanes read last (lanes 12-15 of every 16-lane row) stored the new
-values, and every parity test caught it.  The decoder's 16-byte row stores
-(codes with four or more survivor dwords per lane and row) rely on the
-compiler keeping that distance, so this test disassembles the built code
-objects (the library's own build) and searches every path after every
-12- and 16-byte store -- fall-through, taken branches and loop back-edges --
-for an instruction that writes one of its data VGPRs (vector ALU results,
-vector-memory and LDS loads, returning atomics) too early."""
+8 bytes after the store issues; an instruction that writes them too soon
+changes what the last lanes store.  This was measured on MI355X with a row
+layout whose 16-byte stores were followed directly by such a write: the
+lanes read last (lanes 12-15 of every 16-lane row) stored the new values,
+and every parity test caught it.  The compiler does not reliably keep the
+distance (a later build of the 256-state kernel placed such a write right
+after a 16-byte row store), so the row stores are 8 bytes wide, which have
+no such window.  This test disassembles the built code objects (the
+library's own build) and checks that no 12- or 16-byte buffer store is
+left; should one come back, every path after it -- fall-through, taken
+branches and loop back-edges -- is searched for an instruction that writes
+one of its data VGPRs (vector ALU results, vector-memory and LDS loads,
+returning atomics) within MIN_DISTANCE instructions."""
 import glob
 import os
 import re
@@ -152,4 +151,4 @@ def test_row_store_data_registers_not_overwritten_at_once(tmp_path):
         total += n
         assert not bad, "%s: a store's data VGPRs are overwritten %d instructions later: %s / %s" % (
             os.path.basename(obj), bad[0][2], bad[0][0], bad[0][1])
-    assert total > 0, "no 16-byte row stores found (K >= 8 codes store four dwords per lane and row)"
+    assert total == 0, "%d buffer stores of more than 8 bytes in the decoder kernels" % total
