@@ -28,9 +28,25 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-I", INCLUDE, "-I", CSRC]
 
 
+def _registry_rows(macro: str, csrc: str = CSRC) -> int:
+    """Rows X(...) of one list macro of the registry header."""
+    with open(os.path.join(csrc, "pbvd_registry.hpp")) as f:
+        text = f.read()
+    body = text[text.index("#define " + macro):]
+    rows = 0
+    for line in body.split("\n")[1:]:
+        if not re.match(r"^\s*X\(\d+,", line):
+            break
+        rows += 1
+    return rows
+
+
 def num_codes() -> int:
-    with open(os.path.join(CSRC, "pbvd_registry.hpp")) as f:
-        return len(re.findall(r"^\s*X\(\d+,", f.read(), flags=re.M))
+    return _registry_rows("PBVD_CODE_LIST(X)")
+
+
+def num_pairs() -> int:
+    return _registry_rows("PBVD_PAIR_LIST(X)")
 
 
 def _run(cmd):
@@ -56,6 +72,9 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
     for i in range(num_codes()):
         units.append((os.path.join(csrc, "pbvd_code_inst.hip"),
                       os.path.join(build_dir, "code_%02d.o" % i), ["-DPBVD_CODE_IDX=%d" % i]))
+    for i in range(num_pairs()):
+        units.append((os.path.join(csrc, "pbvd_pair_inst.hip"),
+                      os.path.join(build_dir, "pair_%02d.o" % i), ["-DPBVD_PAIR_IDX=%d" % i]))
     for k in range(3, 10):
         units.append((os.path.join(csrc, "pbvd_wave_inst.hip"),
                       os.path.join(build_dir, "wave_k%d.o" % k), ["-DPBVD_WAVE_K=%d" % k]))

@@ -57,7 +57,8 @@ struct PbRec {
 }  // namespace
 
 pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
-                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves) {
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves,
+                            bool pair_tiles) {
     std::vector<std::vector<PbRec>> per_code(cs.n);
     std::vector<std::pair<int64_t, int64_t>> outs;
     outs.reserve((size_t)n_frames);
@@ -132,6 +133,10 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 wl->descs.push_back(pbvd::LaneDesc{r.sym, r.out_bit, r.len, r.store0, r.dec_end, r.flags});
         }
     }
+    // register-kernel tiles per code (heads, 64 lane descriptors each),
+    // emitted after the loop: code by code, a pair's two codes merged
+    std::vector<std::vector<pbvd::TileHead>> th(cs.n);
+    std::vector<std::vector<pbvd::LaneDesc>> tl(cs.n);
     for (int ci = 0; ci < cs.n; ++ci) {
         const pbvd_code &c = cs.codes[ci];
         const int64_t U = pbvd::trip_stages(c.K);
@@ -184,7 +189,6 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             if (x.len != y.len) return x.len > y.len;
             return x.dec_end < y.dec_end;
         });
-        wl->groups[ci].tile_begin = (int64_t)wl->heads.size();
         size_t i = 0;
         while (i < v.size()) {
             size_t e = std::min(v.size(), i + pw);
@@ -215,7 +219,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 d.store0 = r.store0;
                 d.dec_end = r.dec_end;
                 d.flags = k < e ? r.flags : (r.flags & ~pbvd::kLaneActive);
-                for (int g = 0; g < (1 << lb); ++g) wl->lanes.push_back(d);
+                for (int g = 0; g < (1 << lb); ++g) tl[ci].push_back(d);
                 if (r.len != v[i].len || r.store0 != v[i].store0 || r.dec_end != v[i].dec_end) uniform = false;
                 if (r.store0 != v[i].store0) same_store0 = false;
                 if (r.len > h.len) h.len = r.len;
@@ -226,12 +230,68 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             }
             h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0) |
                       (uniform ? pbvd::kTileUniform : 0) | (same_store0 ? pbvd::kTileStore0 : 0);
-            wl->heads.push_back(h);
+            th[ci].push_back(h);
             i = e;
         }
-        wl->groups[ci].n_tiles = (int64_t)wl->heads.size() - wl->groups[ci].tile_begin;
         wl->groups[ci].sp_wave_dwords = slot_dwords(c, lb);
         wl->groups[ci].lb = lb;
+    }
+
+    // registered pairs among the register codes (one launch for both)
+    int partner[kMaxCodes], pair_of[kMaxCodes];
+    bool second[kMaxCodes];
+    for (int ci = 0; ci < cs.n; ++ci) partner[ci] = pair_of[ci] = -1, second[ci] = false;
+    auto register_code = [&](int ci) { return cs.idx[ci] >= 0 && cs.lb[ci] >= 0 && cs.lb[ci] <= 3; };
+    for (int ci = 0; pair_tiles && ci < cs.n; ++ci) {
+        for (int cj = ci + 1; cj < cs.n && partner[ci] < 0; ++cj) {
+            const pbvd_code &a = cs.codes[ci], &b = cs.codes[cj];
+            if (partner[cj] >= 0 || !register_code(ci) || !register_code(cj) || cs.lb[ci] != cs.lb[cj] ||
+                a.pm_bits != 16 || b.pm_bits != 16 || a.input_kind != b.input_kind || th[ci].empty() ||
+                th[cj].empty())
+                continue;
+            bool ci_first = true;
+            const int p = find_pair(cs.idx[ci], cs.idx[cj], &ci_first);
+            if (p < 0) continue;
+            partner[ci] = cj;
+            partner[cj] = ci;
+            pair_of[ci] = pair_of[cj] = p;
+            second[ci] = !ci_first;
+            second[cj] = ci_first;
+        }
+    }
+    for (int ci = 0; ci < cs.n; ++ci) {
+        if (!register_code(ci) || (partner[ci] >= 0 && partner[ci] < ci)) continue;
+        TileGroup &g = wl->groups[ci];
+        g.tile_begin = (int64_t)wl->heads.size();
+        if (partner[ci] < 0) {
+            wl->heads.insert(wl->heads.end(), th[ci].begin(), th[ci].end());
+            wl->lanes.insert(wl->lanes.end(), tl[ci].begin(), tl[ci].end());
+            g.n_tiles = (int64_t)th[ci].size();
+            continue;
+        }
+        // both codes' tiles, longest first over the two; the tiles of the
+        // pair's second code carry kTileCode1
+        const int cj = partner[ci];
+        std::vector<std::pair<int, size_t>> order;
+        order.reserve(th[ci].size() + th[cj].size());
+        for (size_t k = 0; k < th[ci].size(); ++k) order.emplace_back(ci, k);
+        for (size_t k = 0; k < th[cj].size(); ++k) order.emplace_back(cj, k);
+        std::stable_sort(order.begin(), order.end(), [&](const std::pair<int, size_t> &x,
+                                                         const std::pair<int, size_t> &y) {
+            return th[x.first][x.second].len > th[y.first][y.second].len;
+        });
+        for (const auto &o : order) {
+            pbvd::TileHead h = th[o.first][o.second];
+            if (second[o.first]) h.flags |= pbvd::kTileCode1;
+            wl->heads.push_back(h);
+            const size_t l0 = o.second * (size_t)pbvd::kWave;
+            wl->lanes.insert(wl->lanes.end(), tl[o.first].begin() + l0, tl[o.first].begin() + l0 + pbvd::kWave);
+        }
+        g.n_tiles = (int64_t)order.size();
+        g.sp_wave_dwords = std::max(g.sp_wave_dwords, wl->groups[cj].sp_wave_dwords);
+        g.pair = pair_of[ci];
+        wl->groups[cj].tile_begin = g.tile_begin;
+        wl->groups[cj].n_tiles = 0;
     }
     return PBVD_OK;
 }
@@ -306,7 +366,7 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
         req.lb = g.lb;
         req.grid = (unsigned)ceil_div(a.n_tiles, waves_per_block);
         req.stream = stream;
-        hipError_t e = launch_tiles(cs.idx[ci], req);
+        hipError_t e = g.pair >= 0 ? launch_tiles_pair(g.pair, req) : launch_tiles(cs.idx[ci], req);
         if (e != hipSuccess) return fail_hip(e, "batch kernel launch");
     }
     return PBVD_OK;
@@ -436,7 +496,7 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     WorkList wl;
     pbvd_status st;
     try {
-        st = build_work_list(cs, frames, n_frames, sym_bytes, out_bytes, &wl, true);
+        st = build_work_list(cs, frames, n_frames, sym_bytes, out_bytes, &wl, true, true);
     } catch (...) {
         st = fail(PBVD_ENOMEM, "host allocation failed while building the work list");
     }

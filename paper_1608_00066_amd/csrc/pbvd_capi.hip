@@ -46,6 +46,15 @@ using TileLaunchFn = hipError_t (*)(const pbvd::TileLaunchRequest &);
 #define PBVD_TFN(i, K, R, g0, g1, g2, g3) &pbvd::launch_tiles<i>,
 const TileLaunchFn kTileLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_TFN)};
 #undef PBVD_TFN
+#define PBVD_PFN(i, a, b) &pbvd::launch_tiles_pair<i>,
+const TileLaunchFn kPairLaunchTable[kNumPairs] = {PBVD_PAIR_LIST(PBVD_PFN)};
+#undef PBVD_PFN
+struct RegisteredPair {
+    int first, second;  // registry indices
+};
+#define PBVD_PROW(i, a, b) {a, b},
+const RegisteredPair kRegisteredPairs[kNumPairs] = {PBVD_PAIR_LIST(PBVD_PROW)};
+#undef PBVD_PROW
 
 int find_code(const pbvd_code &c) {
     for (int i = 0; i < kNumCodes; ++i) {
@@ -303,6 +312,21 @@ pbvd_status check_code(const pbvd_code &c, int *idx_out) {
 
 hipError_t launch_tiles(int code_idx, const pbvd::TileLaunchRequest &req) {
     return kTileLaunchTable[code_idx](req);
+}
+
+int find_pair(int idx_a, int idx_b, bool *a_first) {
+    for (int i = 0; i < kNumPairs; ++i) {
+        const RegisteredPair &p = kRegisteredPairs[i];
+        if ((p.first == idx_a && p.second == idx_b) || (p.first == idx_b && p.second == idx_a)) {
+            *a_first = p.first == idx_a;
+            return i;
+        }
+    }
+    return -1;
+}
+
+hipError_t launch_tiles_pair(int pair_idx, const pbvd::TileLaunchRequest &req) {
+    return kPairLaunchTable[pair_idx](req);
 }
 
 }  // namespace pbvd_host

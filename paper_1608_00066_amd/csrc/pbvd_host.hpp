@@ -83,6 +83,10 @@ int64_t workspace_budget_bytes();
 
 // Launches the tile kernel of registry entry code_idx.
 hipError_t launch_tiles(int code_idx, const pbvd::TileLaunchRequest &req);
+// Registered pair of the registry codes idx_a and idx_b (either order), -1 if
+// none; *a_first tells whether idx_a is the pair's first code.
+int find_pair(int idx_a, int idx_b, bool *a_first);
+hipError_t launch_tiles_pair(int pair_idx, const pbvd::TileLaunchRequest &req);
 
 // ---- batched decoding work list --------------------------------------------
 
@@ -113,6 +117,10 @@ struct TileGroup {
     int64_t tile_begin = 0, n_tiles = 0;
     int64_t sp_wave_dwords = 0;
     int lb = 0;
+    // register codes of a registered pair: the group of the first code of
+    // the two in the code set holds both codes' tiles (pair launch), the
+    // other's is empty
+    int pair = -1;
 };
 
 // The PBs of every state-parallel code of one constraint length, for one
@@ -140,8 +148,11 @@ struct WorkList {
 // Builds the work list of `frames` (validated against the buffer sizes).
 // fuse_waves: the state-parallel codes of one K share one fused group (and
 // their own groups stay empty); else each code has its own group.
+// pair_tiles: register codes that form a registered pair (same lanes per PB,
+// 16-bit metrics, same input kind) share one group, launched as one.
 pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t n_frames,
-                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves = false);
+                            int64_t sym_bytes, int64_t out_bytes, WorkList *wl, bool fuse_waves = false,
+                            bool pair_tiles = false);
 
 // Launches the tile kernels of one code group: tiles [g.tile_begin, + g.n_tiles)
 // of the uploaded work list, at most `per_launch` waves per launch sharing

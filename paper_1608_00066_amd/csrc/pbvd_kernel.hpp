@@ -1235,8 +1235,9 @@ enum { kLaneKnown = 1, kLaneArgmin = 2, kLaneActive = 4 };
 // kTileUniform: every lane has the same len, store0 and dec_end, so the tile
 // runs the uniform-wave decode body (phase-aligned traceback); kTileStore0:
 // every lane has the same store0 (lengths may differ), so the tile's
-// traceback is phase-aligned too, with a per-lane start and end
-enum { kTileWide = 1, kTileFinal = 2, kTileUniform = 4, kTileStore0 = 8 };
+// traceback is phase-aligned too, with a per-lane start and end; kTileCode1:
+// in a launch of a pair of codes, the tile's PBs are of the second code
+enum { kTileWide = 1, kTileFinal = 2, kTileUniform = 4, kTileStore0 = 8, kTileCode1 = 16 };
 
 struct TileArgs {
     const uint8_t *syms;
@@ -1250,23 +1251,17 @@ struct TileArgs {
     int64_t n_tiles;
 };
 
+// One tile of a batch (the wave's PBs, their descriptors and survivor slot).
 template <class C, class P, int KIND, int LB>
-__global__ void __launch_bounds__(256)
-    __attribute__((amdgpu_waves_per_eu(waves_per_eu_target<(C::NR >> LB) * (int)(sizeof(typename P::T) / 4)>())))
-    decode_tiles_kernel(const TileArgs a) {
+__device__ __forceinline__ void tile_body(const TileArgs &a, int64_t wave_local, int lane, const TileHead &h,
+                                          int tflags) {
     using LY = Layout<C, P, LB>;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
-                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    if (wave_local >= a.n_tiles) return;
     const int64_t tile = a.tile_begin + wave_local;
-    const TileHead h = a.heads[tile];
     const LaneDesc d = a.lanes[tile * kWave + lane];
 
     WaveJob j;
     j.len = __builtin_amdgcn_readfirstlane(h.len);
     j.store0_min = __builtin_amdgcn_readfirstlane(h.store0_min);
-    const int tflags = __builtin_amdgcn_readfirstlane(h.flags);
     j.fetch_safe = (tflags & kTileWide) != 0;
     j.i_safe = j.fetch_safe ? j.len : -1;
     j.need_final = (tflags & kTileFinal) != 0;
@@ -1298,6 +1293,38 @@ __global__ void __launch_bounds__(256)
     } else {
         decode_body<C, P, KIND, true, LB>(j, rows);
     }
+}
+
+template <class C, class P, int KIND, int LB>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu_target<(C::NR >> LB) * (int)(sizeof(typename P::T) / 4)>())))
+    decode_tiles_kernel(const TileArgs a) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave_local >= a.n_tiles) return;
+    const TileHead h = a.heads[a.tile_begin + wave_local];
+    tile_body<C, P, KIND, LB>(a, wave_local, lane, h, __builtin_amdgcn_readfirstlane(h.flags));
+}
+
+// Batch kernel for a pair of codes of one constraint length: the tiles of
+// both in one launch (longest first over both), each tile decoded with the
+// code its head names (kTileCode1: the second).  One launch instead of one
+// per code: no fork and join of streams, and the waves of both codes share
+// the compute units from the first to the last tile.
+template <class C0, class C1, class P, int KIND, int LB>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(waves_per_eu_target<(C0::NR >> LB) * (int)(sizeof(typename P::T) / 4)>())))
+    decode_tiles_pair_kernel(const TileArgs a) {
+    static_assert(C0::K == C1::K, "a pair shares one trellis size");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave_local = (int64_t)blockIdx.x * (blockDim.x / kWave) +
+                               __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (wave_local >= a.n_tiles) return;
+    const TileHead h = a.heads[a.tile_begin + wave_local];
+    const int tflags = __builtin_amdgcn_readfirstlane(h.flags);
+    if (tflags & kTileCode1) tile_body<C1, P, KIND, LB>(a, wave_local, lane, h, tflags);
+    else tile_body<C0, P, KIND, LB>(a, wave_local, lane, h, tflags);
 }
 
 }  // namespace pbvd

@@ -38,6 +38,17 @@
 constexpr int kNumCodes = 0 PBVD_CODE_LIST(PBVD_COUNT_ONE);
 #undef PBVD_COUNT_ONE
 
+// Pairs of registered codes of one constraint length whose batch tiles share
+// one launch of the register kernel (16-bit metrics): X(index, code a, code b)
+// with the registry indices above.  The rate-1/2 and rate-1/3 K=7 codes that
+// are mixed in one batch of frames.
+#define PBVD_PAIR_LIST(X) \
+    X(0, 1, 2)
+
+#define PBVD_COUNT_PAIR(i, a, b) +1
+constexpr int kNumPairs = 0 PBVD_PAIR_LIST(PBVD_COUNT_PAIR);
+#undef PBVD_COUNT_PAIR
+
 struct RegisteredCode {
     int K, R;
     uint32_t gen[4];
@@ -73,6 +84,10 @@ template <int IDX>
 hipError_t launch_code(const LaunchRequest &req);
 template <int IDX>
 hipError_t launch_tiles(const TileLaunchRequest &req);
+// Implemented by the translation unit compiled for pair index IDX (tiles of
+// both codes in one launch, 16-bit metrics only).
+template <int IDX>
+hipError_t launch_tiles_pair(const TileLaunchRequest &req);
 
 // State-parallel kernel (one wave per PB, run-time generators).
 struct WaveLaunchRequest {

@@ -113,6 +113,19 @@ def test_batch_equal_frames_uniform_tiles(torch, pbvd, lanes):
     check_batch(torch, pbvd, codes, 150, 1000, 1000, seed=31)
 
 
+@pytest.mark.parametrize("lanes,kind", [(1, 1), (2, 0)], ids=["lanes1-hard", "lanes2-soft"])
+def test_batch_code_pair_one_launch(torch, pbvd, lanes, kind):
+    """The registered pair K=7 r1/2 (171,133) + r1/3 (133,171,165) decodes in
+    one tile launch (each tile names its code): listed in the other order,
+    with different D and L, another code between them, hard and soft input;
+    every frame against the oracle."""
+    codes = [dict(K=7, gens=(0o133, 0o171, 0o165), D=96, L=42, input_kind=kind, lanes_per_pb=lanes),
+             dict(K=5, gens=(0o23, 0o35), D=128, L=30, input_kind=kind),
+             dict(K=7, gens=(0o171, 0o133), D=64, L=30, input_kind=kind, lanes_per_pb=lanes)]
+    log("batch pair lanes %d kind %d: 200 frames, lengths 1..2500" % (lanes, kind))
+    check_batch(torch, pbvd, codes, 200, 1, 2500, seed=61 + lanes)
+
+
 @pytest.mark.parametrize("mapping", [0, 2], ids=["auto", "wave"])
 def test_batch_graph_capture_replays(torch, pbvd, mapping):
     """The decode call only launches kernels (the persistent launch's work
