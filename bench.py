@@ -349,16 +349,18 @@ def bench_batched(torch, steps: int, fixed=None):
         for _ in range(3):
             g.replay()
         torch.cuda.synchronize()
-        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(steps)]
+        # the steps back to back, as a stream of batches runs: one pair of
+        # events around all of them (events between replays would add their
+        # own gaps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
-        for e0, e1 in ev:
-            e0.record()
+        e0.record()
+        for _ in range(steps):
             g.replay()
-            e1.record()
+        e1.record()
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) / steps
-        dev = sum(e0.elapsed_time(e1) for e0, e1 in ev) / steps * 1e-3
+        dev = e0.elapsed_time(e1) / steps * 1e-3
         del g
     batched = out.clone()
     log("batched: plain per-frame launches")
