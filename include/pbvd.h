@@ -264,7 +264,10 @@ void pbvd_destroy(pbvd_plan *p);
  * are packed regardless of frame boundaries, so thousands of short frames
  * fill the GPU as well as one long stream does; per code mapping:
  *   register kernel (PBVD_MAP_LANES / AUTO): tiles of 64 >> lb PBs of one
- *     code, one launch per code;
+ *     code, one launch per code, except that the two codes of a pair the
+ *     library registers (K=7 (171,133) with (133,171,165)) share one launch
+ *     when they have the same lanes per PB, 16-bit metrics and input kind
+ *     (each tile decoded with its own code);
  *   state-parallel kernel (PBVD_MAP_WAVE): the PBs of every such code of one
  *     K in ONE persistent launch, longest first, waves taking PBs from work
  *     counters (one per XCD) that a fill kernel zeroes at the start of each
