@@ -73,8 +73,10 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
         units.append((os.path.join(csrc, "pbvd_code_inst.hip"),
                       os.path.join(build_dir, "code_%02d.o" % i), ["-DPBVD_CODE_IDX=%d" % i]))
     for i in range(num_pairs()):
-        units.append((os.path.join(csrc, "pbvd_pair_inst.hip"),
-                      os.path.join(build_dir, "pair_%02d.o" % i), ["-DPBVD_PAIR_IDX=%d" % i]))
+        for kind in (0, 1):
+            units.append((os.path.join(csrc, "pbvd_pair_inst.hip"),
+                          os.path.join(build_dir, "pair_%02d_%d.o" % (i, kind)),
+                          ["-DPBVD_PAIR_IDX=%d" % i, "-DPBVD_PAIR_KIND=%d" % kind]))
     for k in range(3, 10):
         units.append((os.path.join(csrc, "pbvd_wave_inst.hip"),
                       os.path.join(build_dir, "wave_k%d.o" % k), ["-DPBVD_WAVE_K=%d" % k]))
@@ -109,9 +111,11 @@ def build(jobs: int | None = None, verbose: bool = False, csrc: str = CSRC,
             print("built", os.path.basename(obj), flush=True)
         return obj
 
-    # longest units first (K=9 kernels)
+    # longest units first: the pair kernels, then the per-code kernels
+    order = {"pair": 0, "code": 1}
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(compile_unit, sorted(units, key=lambda u: u[1])))
+        objs = list(ex.map(compile_unit, sorted(
+            units, key=lambda u: (order.get(os.path.basename(u[1]).split("_")[0], 2), u[1]))))
     tmp = lib + ".tmp%d" % os.getpid()
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *sorted(objs)])
     os.replace(tmp, lib)

@@ -48,6 +48,16 @@ pbvd_status make_code_set(const pbvd_code *codes, int32_t n, CodeSet *out, int a
 
 namespace {
 
+// Waves per workgroup of a tile launch: 4 (PBVD_TILE_WAVES_PER_BLOCK = 1, 2
+// or 4 overrides it).
+int tile_waves_per_block() {
+    if (const char *env = getenv("PBVD_TILE_WAVES_PER_BLOCK")) {
+        const int w = atoi(env);
+        if (w == 1 || w == 2 || w == 4) return w;
+    }
+    return pbvd::kBlockThreads / pbvd::kWave;
+}
+
 // One parallel block of one frame (Sec. III-A), in the batch's coordinates.
 struct PbRec {
     int64_t sym, out_bit;
@@ -207,6 +217,7 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
             pbvd::TileHead h{};
             h.len = 0;
             h.store0_min = 0x7fffffff;
+            int64_t i_safe = INT64_MAX;
             bool wide = true, final_needed = false, uniform = true, same_store0 = true;
             for (size_t k = i; k < i + pw; ++k) {
                 // PBs past the tile's repeat its first PB, inactive; every
@@ -225,9 +236,16 @@ pbvd_status build_work_list(const CodeSet &cs, const pbvd_frame *frames, int64_t
                 if (r.len > h.len) h.len = r.len;
                 if (r.store0 < h.store0_min) h.store0_min = r.store0;
                 const int64_t last_trip = ((r.len - 1) / U) * U;
-                if (r.sym + last_trip * c.R + 4 * ND > sym_bytes) wide = false;
+                if (r.sym + last_trip * c.R + 4 * ND > sym_bytes) {
+                    // the lane's wide fetches are in bounds up to stage t
+                    wide = false;
+                    const int64_t room = sym_bytes - 4 * ND - r.sym;
+                    i_safe = std::min(i_safe, room < 0 ? -1 : room / c.R);
+                }
                 if (r.flags & pbvd::kLaneArgmin) final_needed = true;
             }
+            // only the trips past the first unsafe fetch take byte loads
+            h.i_safe = wide ? h.len : (int32_t)std::min<int64_t>(i_safe, h.len);
             h.flags = (wide ? pbvd::kTileWide : 0) | (final_needed ? pbvd::kTileFinal : 0) |
                       (uniform ? pbvd::kTileUniform : 0) | (same_store0 ? pbvd::kTileStore0 : 0);
             th[ci].push_back(h);
@@ -348,7 +366,7 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
         }
         return PBVD_OK;
     }
-    const int waves_per_block = pbvd::kBlockThreads / pbvd::kWave;
+    const int waves_per_block = tile_waves_per_block();
     for (int64_t t0 = 0; t0 < g.n_tiles; t0 += per_launch) {
         pbvd::TileLaunchRequest req{};
         pbvd::TileArgs &a = req.args;
@@ -365,6 +383,7 @@ pbvd_status launch_group(const CodeSet &cs, int ci, const TileGroup &g, const ui
         req.input_kind = cs.codes[ci].input_kind;
         req.lb = g.lb;
         req.grid = (unsigned)ceil_div(a.n_tiles, waves_per_block);
+        req.block_threads = (unsigned)(waves_per_block * pbvd::kWave);
         req.stream = stream;
         hipError_t e = g.pair >= 0 ? launch_tiles_pair(g.pair, req) : launch_tiles(cs.idx[ci], req);
         if (e != hipSuccess) return fail_hip(e, "batch kernel launch");

@@ -46,8 +46,8 @@ using TileLaunchFn = hipError_t (*)(const pbvd::TileLaunchRequest &);
 #define PBVD_TFN(i, K, R, g0, g1, g2, g3) &pbvd::launch_tiles<i>,
 const TileLaunchFn kTileLaunchTable[kNumCodes] = {PBVD_CODE_LIST(PBVD_TFN)};
 #undef PBVD_TFN
-#define PBVD_PFN(i, a, b) &pbvd::launch_tiles_pair<i>,
-const TileLaunchFn kPairLaunchTable[kNumPairs] = {PBVD_PAIR_LIST(PBVD_PFN)};
+#define PBVD_PFN(i, a, b) {&pbvd::launch_tiles_pair<i, pbvd::kSoftI8>, &pbvd::launch_tiles_pair<i, pbvd::kHardU8>},
+const TileLaunchFn kPairLaunchTable[kNumPairs][2] = {PBVD_PAIR_LIST(PBVD_PFN)};
 #undef PBVD_PFN
 struct RegisteredPair {
     int first, second;  // registry indices
@@ -326,7 +326,8 @@ int find_pair(int idx_a, int idx_b, bool *a_first) {
 }
 
 hipError_t launch_tiles_pair(int pair_idx, const pbvd::TileLaunchRequest &req) {
-    return kPairLaunchTable[pair_idx](req);
+    if (req.input_kind != pbvd::kSoftI8 && req.input_kind != pbvd::kHardU8) return hipErrorInvalidValue;
+    return kPairLaunchTable[pair_idx][req.input_kind == pbvd::kHardU8 ? 1 : 0](req);
 }
 
 }  // namespace pbvd_host

@@ -44,7 +44,7 @@ hipError_t launch_one(const LaunchRequest &req) {
 template <class C, class P, int KIND, int LB>
 hipError_t launch_tiles_lb(const TileLaunchRequest &req) {
     if constexpr (lanes_supported<C, P, LB>()) {
-        hipLaunchKernelGGL((decode_tiles_kernel<C, P, KIND, LB>), dim3(req.grid), dim3(kBlockThreads), 0,
+        hipLaunchKernelGGL((decode_tiles_kernel<C, P, KIND, LB>), dim3(req.grid), dim3(req.block_threads), 0,
                            req.stream, req.args);
         return hipGetLastError();
     } else {

@@ -1228,8 +1228,9 @@ struct LaneDesc {
 struct TileHead {
     int32_t len;        // longest lane
     int32_t store0_min; // lowest first-traced stage
-    int32_t flags;      // kTileWide | kTileFinal | kTileUniform
-    int32_t pad;
+    int32_t flags;      // kTileWide | kTileFinal | kTileUniform | kTileStore0 | kTileCode1
+    int32_t i_safe;     // without kTileWide: last stage whose wide symbol fetch is
+                        // in bounds for every lane (-1: none); later trips load bytes
 };
 enum { kLaneKnown = 1, kLaneArgmin = 2, kLaneActive = 4 };
 // kTileUniform: every lane has the same len, store0 and dec_end, so the tile
@@ -1263,7 +1264,7 @@ __device__ __forceinline__ void tile_body(const TileArgs &a, int64_t wave_local,
     j.len = __builtin_amdgcn_readfirstlane(h.len);
     j.store0_min = __builtin_amdgcn_readfirstlane(h.store0_min);
     j.fetch_safe = (tflags & kTileWide) != 0;
-    j.i_safe = j.fetch_safe ? j.len : -1;
+    j.i_safe = j.fetch_safe ? j.len : __builtin_amdgcn_readfirstlane(h.i_safe);
     j.need_final = (tflags & kTileFinal) != 0;
     j.in_end = a.syms + a.sym_bytes;
     j.in = a.syms + d.sym;

@@ -1,9 +1,11 @@
 // Batch tile kernels of one pair of registered codes (both codes' tiles in
-// one launch).  Compiled once per pair with -DPBVD_PAIR_IDX=<index>.
+// one launch).  Compiled once per pair and input kind with
+// -DPBVD_PAIR_IDX=<index> -DPBVD_PAIR_KIND=<kSoftI8 or kHardU8>, so the
+// units build in parallel.
 #include "pbvd_registry.hpp"
 
-#ifndef PBVD_PAIR_IDX
-#error "compile with -DPBVD_PAIR_IDX=<pair index>"
+#if !defined(PBVD_PAIR_IDX) || !defined(PBVD_PAIR_KIND)
+#error "compile with -DPBVD_PAIR_IDX=<pair index> -DPBVD_PAIR_KIND=<input kind>"
 #endif
 
 namespace pbvd {
@@ -34,7 +36,7 @@ template <class C0, class C1, int KIND, int LB>
 hipError_t launch_pair_lb(const TileLaunchRequest &req) {
     if constexpr (lanes_supported<C0, PM16, LB>() && lanes_supported<C1, PM16, LB>()) {
         hipLaunchKernelGGL((decode_tiles_pair_kernel<C0, C1, PM16, KIND, LB>), dim3(req.grid),
-                           dim3(kBlockThreads), 0, req.stream, req.args);
+                           dim3(req.block_threads), 0, req.stream, req.args);
         return hipGetLastError();
     } else {
         return hipErrorInvalidValue;
@@ -54,16 +56,15 @@ hipError_t launch_pair_kind(const TileLaunchRequest &req) {
 
 }  // namespace
 
-template <int IDX>
+template <int IDX, int KIND>
 hipError_t launch_tiles_pair(const TileLaunchRequest &req) {
     using C0 = typename PairAt<IDX>::first;
     using C1 = typename PairAt<IDX>::second;
     static_assert(C0::K == C1::K, "a pair shares one trellis size");
-    if (req.pm_bits != 16) return hipErrorInvalidValue;
-    return req.input_kind == kHardU8 ? launch_pair_kind<C0, C1, kHardU8>(req)
-                                     : launch_pair_kind<C0, C1, kSoftI8>(req);
+    if (req.pm_bits != 16 || req.input_kind != KIND) return hipErrorInvalidValue;
+    return launch_pair_kind<C0, C1, KIND>(req);
 }
 
-template hipError_t launch_tiles_pair<PBVD_PAIR_IDX>(const TileLaunchRequest &req);
+template hipError_t launch_tiles_pair<PBVD_PAIR_IDX, PBVD_PAIR_KIND>(const TileLaunchRequest &req);
 
 }  // namespace pbvd

@@ -76,6 +76,7 @@ struct TileLaunchRequest {
     int input_kind;
     int lb;
     unsigned grid;
+    unsigned block_threads;  // 64, 128 or 256 (one wave per tile)
     hipStream_t stream;
 };
 
@@ -84,9 +85,9 @@ template <int IDX>
 hipError_t launch_code(const LaunchRequest &req);
 template <int IDX>
 hipError_t launch_tiles(const TileLaunchRequest &req);
-// Implemented by the translation unit compiled for pair index IDX (tiles of
-// both codes in one launch, 16-bit metrics only).
-template <int IDX>
+// Implemented by the translation unit compiled for pair index IDX and input
+// kind KIND (tiles of both codes in one launch, 16-bit metrics only).
+template <int IDX, int KIND>
 hipError_t launch_tiles_pair(const TileLaunchRequest &req);
 
 // State-parallel kernel (one wave per PB, run-time generators).
