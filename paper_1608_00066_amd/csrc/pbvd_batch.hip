@@ -500,17 +500,33 @@ pbvd_status pbvd_batch_set_frames(pbvd_batch *b, const pbvd_frame *frames, int64
     if (!b) return fail(PBVD_EINVAL, "batch is NULL");
     if (n_frames < 0 || (n_frames > 0 && !frames)) return fail(PBVD_EINVAL, "bad frame array");
     if (sym_bytes < 0 || out_bytes < 0) return fail(PBVD_EINVAL, "negative buffer size");
-    // codes that leave the lanes per PB open: one lane per PB when the code's
-    // PBs give every SIMD a wave, the largest lane group otherwise
+    // codes that leave the lanes per PB open: one lane per PB when the PBs
+    // of the launch give every SIMD a wave, the largest lane group otherwise
+    // (the two codes of a registered pair share a launch: their PBs count
+    // together, and they take one width so that they do share it)
     CodeSet cs = b->cs;
     {
         int64_t pbs[kMaxCodes] = {};
         for (int64_t f = 0; f < n_frames; ++f)
             if (frames[f].code >= 0 && frames[f].code < cs.n && frames[f].n_bits > 0)
                 pbs[frames[f].code] += ceil_div(frames[f].n_bits, cs.codes[frames[f].code].D);
-        for (int ci = 0; ci < cs.n; ++ci)
-            if (requested_lb(cs.codes[ci]) < 0 && cs.idx[ci] >= 0)
-                cs.lb[ci] = ceil_div(pbs[ci], pbvd::kWave) >= 1024 ? 0 : max_lb(cs.codes[ci]);
+        for (int ci = 0; ci < cs.n; ++ci) {
+            if (requested_lb(cs.codes[ci]) >= 0 || cs.idx[ci] < 0) continue;
+            int64_t n = pbs[ci];
+            int top = max_lb(cs.codes[ci]);
+            for (int cj = 0; cj < cs.n; ++cj) {
+                bool first = true;
+                if (cj == ci || requested_lb(cs.codes[cj]) >= 0 || cs.idx[cj] < 0 ||
+                    cs.codes[ci].pm_bits != 16 || cs.codes[cj].pm_bits != 16 ||
+                    cs.codes[ci].input_kind != cs.codes[cj].input_kind ||
+                    find_pair(cs.idx[ci], cs.idx[cj], &first) < 0)
+                    continue;
+                n += pbs[cj];
+                top = std::min(top, max_lb(cs.codes[cj]));
+                break;
+            }
+            cs.lb[ci] = ceil_div(n, pbvd::kWave) >= 1024 ? 0 : top;
+        }
     }
     WorkList wl;
     pbvd_status st;

@@ -126,6 +126,19 @@ def test_batch_code_pair_one_launch(torch, pbvd, lanes, kind):
     check_batch(torch, pbvd, codes, 200, 1, 2500, seed=61 + lanes)
 
 
+def test_batch_pair_auto_lanes_counts_both_codes(torch, pbvd):
+    """Codes of a registered pair that leave the lanes per PB open share one
+    launch, so the library sizes their lane groups by the PBs of both: each
+    code alone has fewer than 1,024 waves of PBs (two lanes per PB would be
+    chosen), together more (one lane per PB, 64 PBs per tile).  Every frame
+    against the oracle."""
+    codes = [dict(K=7, gens=(0o171, 0o133), D=64, L=42), dict(K=7, gens=(0o133, 0o171, 0o165), D=64, L=42)]
+    log("batch pair, auto lanes: 800 frames of 6400 bits")
+    _, _, _, _, info = check_batch(torch, pbvd, codes, 800, 6400, 6400, seed=71)
+    assert info["blocks"] == 800 * 100
+    assert info["tiles"] <= info["blocks"] // 64 + 8, "expected one lane per PB: %s" % info
+
+
 @pytest.mark.parametrize("mapping", [0, 2], ids=["auto", "wave"])
 def test_batch_graph_capture_replays(torch, pbvd, mapping):
     """The decode call only launches kernels (the persistent launch's work
