@@ -362,6 +362,26 @@ def bench_batched(torch, steps: int, fixed=None):
         wall = (time.perf_counter() - t0) / steps
         dev = e0.elapsed_time(e1) / steps * 1e-3
         del g
+        # the same decode, 20 captured in one graph (no graph launch between
+        # them, as a loop that replays a captured sequence of batches runs)
+        per_graph = 20
+        gm = torch.cuda.CUDAGraph()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(gm, stream=side):
+                for _ in range(per_graph):
+                    b.decode(syms, out)
+        torch.cuda.current_stream().wait_stream(side)
+        gm.replay()
+        torch.cuda.synchronize()
+        reps = max(1, steps // per_graph)
+        e0.record()
+        for _ in range(reps):
+            gm.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        multi = e0.elapsed_time(e1) / (reps * per_graph) * 1e-3
+        del gm
     batched = out.clone()
     log("batched: plain per-frame launches")
     t_plain_512 = plain_per_frame(torch, pbvd, [dict(c, D=512) for c in base], frames, syms, out)
@@ -376,6 +396,9 @@ def bench_batched(torch, steps: int, fixed=None):
         "batched_mbps": round(n_bits / wall / 1e6, 1),
         "batched_alu_frac": round(ops / dev / PEAK_ALU_OPS[16], 4),
         "batched_alu_tops": round(ops / dev / 1e12, 3),
+        "batched_multi_graph": {"decodes_per_graph": per_graph, "ms_per_decode": round(multi * 1e3, 4),
+                                "mbps": round(n_bits / multi / 1e6, 1),
+                                "alu_frac": round(ops / multi / PEAK_ALU_OPS[16], 4)},
         "plain_per_frame_d512_mbps": round(n_bits / t_plain_512 / 1e6, 2),
         "plain_per_frame_same_d_mbps": round(n_bits / t_plain_d / 1e6, 2),
         "speedup_vs_plain_d512": round(t_plain_512 / wall, 1),
@@ -433,7 +456,8 @@ def batched_summary(b):
             "best_by_layout": b.get("best_by_layout"),
             "roofline": {"bound": "alu", "achieved": b["batched_alu_tops"], "peak": PEAK_ALU_OPS[16] / 1e12,
                          "unit": "Tops/s", "frac": b["batched_alu_frac"]},
-            "plain_per_frame_mbps": b["plain_per_frame_d512_mbps"]}
+            "plain_per_frame_mbps": b["plain_per_frame_d512_mbps"],
+            "multi_decode_graph": b.get("batched_multi_graph")}
 
 
 def main():
